@@ -1,0 +1,180 @@
+#!/usr/bin/env python
+"""Loop-hafnian throughput on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload grad40] [--pass fwd|fwdbwd]
+
+A step is one pass of the hot path over one batch of synthetic input:
+the 256 N=40 Gaussian-state matrices of the differentiation workload
+(U Haar 40x40, r ~ U[0.5,1.5], gamma ~ CN(0,0.1)), finite-difference-sieve
+sum with double-double accumulation; with --pass fwdbwd the adjoint pass
+(d lhaf / dA, d lhaf / d gamma) runs too.  Inputs are resident in HBM before
+the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6
+
+
+def canonical_flops(m: int, n: int) -> float:
+    """Algorithmic FP64 flops of one term: complex Householder Hessenberg
+    reduction of the m x m matrix (40/3 m^3) plus n complex mat-vecs for the
+    loop moments (8 n m^2)."""
+    return 40.0 / 3.0 * m ** 3 + 8.0 * n * m * m
+
+
+def canonical_flops_bwd(m: int, n: int) -> float:
+    return canonical_flops(m, n) + 8.0 * m ** 3 * math.ceil(2 * math.sqrt(n)) + 24.0 * n * m * m
+
+
+def cpu_baseline(A, g, budget_s: float = 12.0):
+    """The oracle (explicit matrix powers, OpenMP over term ranges) on a
+    bounded sample of the same workload: the first S terms of matrix 0."""
+    from oracle import oracle as O
+    threads = os.cpu_count() or 1
+    O.set_threads(threads)
+    t = time.perf_counter()
+    probe = 8 * threads
+    O.lhaf_sum(A, g, mode="fds", t0=0, t1=probe, scaled=False)
+    dt = time.perf_counter() - t
+    S = int(max(probe, min(2 ** 19, probe * budget_s / max(dt, 1e-6))))
+    t = time.perf_counter()
+    O.lhaf_sum(A, g, mode="fds", t0=0, t1=S, scaled=False)
+    dt = time.perf_counter() - t
+    return dict(value=S / dt, unit="terms/s", cores=O.get_threads(), kind="oracle",
+                sample=f"FDS terms [0,{S}) of matrix 0 of the N=40 batch (explicit matrix powers, "
+                       f"double + Neumaier), {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="grad40")
+    ap.add_argument("--pass", dest="passes", default="fwd", choices=["fwd", "fwdbwd"])
+    ap.add_argument("--sum", default="fds", choices=["fds", "et"])
+    ap.add_argument("--acc", default="dd", choices=["dd", "fp64"])
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(the term sum shards by term ranges across GPUs, see DESIGN.md)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2108_01622_amd import api, inputs
+    from paper_2108_01622_amd import _binding
+
+    dev = torch.device("cuda", 0)
+    A_np, g_np = inputs.grad40(count=args.batch)
+    N = A_np.shape[1]
+    n, m = N // 2, N
+    A = torch.as_tensor(A_np, device=dev)
+    g = torch.as_tensor(g_np, device=dev)
+    terms_per_problem = _binding.term_count(N, sum=args.sum)
+    terms = args.batch * terms_per_problem
+    stream = torch.cuda.current_stream(dev)
+
+    fwd_ms, bwd_ms = [], []
+    out = None
+
+    def step(timed: bool):
+        nonlocal out
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        out = api.lhaf_batched(A, g, sum=args.sum, acc=args.acc)
+        e1.record(stream)
+        if args.passes == "fwdbwd":
+            e2 = torch.cuda.Event(enable_timing=True)
+            e2.record(stream)
+            api.lhaf_backward(A, g, torch.ones_like(out), sum=args.sum, acc=args.acc)
+            e3 = torch.cuda.Event(enable_timing=True)
+            e3.record(stream)
+        if timed:
+            torch.cuda.synchronize()
+            fwd_ms.append(e0.elapsed_time(e1))
+            if args.passes == "fwdbwd":
+                bwd_ms.append(e2.elapsed_time(e3))
+
+    for i in range(args.warmup):
+        step(False)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup step {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(True)
+        print(f"[bench] step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    passes = 2 if args.passes == "fwdbwd" else 1
+    value = passes * terms * args.steps / elapsed
+    fwd_s = np.mean(fwd_ms) / 1e3
+    achieved = canonical_flops(m, n) * terms / fwd_s / 1e12
+    res = {
+        "metric": "lhaf terms/sec (FDS, N=40 Gaussian-state batch of 256; "
+                  + ("forward" if passes == 1 else "forward + backward") + ")",
+        "value": value,
+        "unit": "terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Gaussian-state matrices)",
+        "config": {"workload": f"grad40: {args.batch} x lhaf N={N} complex128, {args.sum.upper()} "
+                               f"{args.acc} accumulation, " + ("fwd" if passes == 1 else "fwd+bwd"),
+                   "global_batch": args.batch, "N": N, "terms_per_lhaf": terms_per_problem,
+                   "sum": args.sum, "acc": args.acc},
+        "roofline": {"bound": "alu", "kernel": "forward_kernel",
+                     "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "per_term_flops": canonical_flops(m, n), "launch_ms": fwd_s * 1e3},
+        "fwd_terms_per_s": terms / fwd_s,
+    }
+    if bwd_ms:
+        bwd_s = np.mean(bwd_ms) / 1e3
+        res["bwd_terms_per_s"] = terms / bwd_s
+        res["bwd_tflops"] = canonical_flops_bwd(m, n) * terms / bwd_s / 1e12
+    # relative error against stored oracle values (tests/golden, oracle-only)
+    gold_path = os.path.join(ROOT, "tests", "golden", "oracle_values.json")
+    if os.path.exists(gold_path) and args.sum == "fds":
+        gold = json.load(open(gold_path))
+        o = out.cpu().numpy()
+        errs = []
+        for key, ent in gold.items():
+            if key.startswith("grad40/"):
+                b = int(key.split("/")[1])
+                if b < args.batch:
+                    ref = complex(*ent["value"])
+                    errs.append(abs(o[b] - ref) / abs(ref))
+        if errs:
+            res["rel_err_vs_oracle"] = {"max": max(errs), "count": len(errs),
+                                        "oracle": "FDS double, explicit matrix powers"}
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(A_np[0], g_np[0])
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,165 @@
+/*
+ * lhaf.h -- C ABI of the MI355X (gfx950) loop-hafnian library.
+ *
+ * Computes complex loop hafnians lhaf(A, gamma) of symmetric matrices, their
+ * repeated-row ("collision") form and their gradients, following
+ * arXiv:2108.01622 (Quesada/Bulmer et al., "The boundary for quantum advantage
+ * in Gaussian boson sampling"), App. B:
+ *   - lhaf(A) = sum over single-pair matchings of products of A_ij over pairs
+ *     and gamma_i over singles (App. B, definition);
+ *   - evaluated as a sum over terms of one fixed perfect matching: the
+ *     eigenvalue-trace inclusion/exclusion sum (App. B.1, Eqs. ET_loop,
+ *     ET_poly) or the finite-difference sieve (App. B.4, Eq. fdsieve), with
+ *     repeated pairs (App. B.2) chosen by the greedy matching of App. B.3;
+ *   - each term is the lambda^n coefficient of exp(sum_k g_k lambda^k),
+ *     g_k = Tr(W^k)/(2k) + u^T W^{k-1} v / 2, W = C X_d (App. B.1/B.2).
+ *
+ * Conventions
+ *   - Complex numbers are interleaved (re, im) doubles: lh_c128 has the layout
+ *     of torch.complex128 / hipDoubleComplex.
+ *   - Matrices are row-major with leading dimension lda (elements).  The
+ *     library reads sym(A) = (A + A^T)/2.
+ *   - Plain lhaf: A's diagonal is ignored; gamma gives the loop weights.
+ *   - Repeated form lhaf(A_r): row/column i is repeated r_i times; two copies
+ *     of mode i couple with A_ii; every copy has loop weight gamma_i (App. A,
+ *     construction of A_n).
+ *   - N = sum of sizes (or of r); odd N is padded with one vertex that has no
+ *     couplings and loop weight 1, which leaves the value unchanged.
+ *   - Limits: N <= 64 per problem.
+ *
+ * Ownership and errors
+ *   - Every pointer belongs to the caller.  Device pointers must stay valid
+ *     until the work queued on `stream` has finished.  Host pointers (r,
+ *     idx_off, opts) are read before the call returns.
+ *   - Arguments are validated synchronously; a non-zero status means nothing
+ *     was queued.  Results are valid after the stream is synchronised.
+ *   - Non-finite inputs give a NaN result and err_est = +Inf.
+ *   - The library keeps no state except one lazily created scratch buffer per
+ *     device (used when opts->workspace is NULL) and the schedule cache read
+ *     from $LHAF_TUNE_CACHE.  Calls on different streams of one device must
+ *     pass their own workspaces.
+ */
+#ifndef LHAF_H
+#define LHAF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  double re, im;
+} lh_c128;
+
+typedef int32_t lh_status;
+#define LH_OK 0
+#define LH_EINVAL 1        /* bad argument (null pointer, negative size ...) */
+#define LH_ESIZE 2         /* problem too large (N > 64) */
+#define LH_EHIP 3          /* a HIP runtime call failed */
+#define LH_ENOMEM 4        /* workspace too small / allocation failed */
+#define LH_EUNSUPPORTED 5  /* option combination not supported */
+
+#define LH_SUM_ET 0  /* eigenvalue-trace inclusion/exclusion (App. B.1/B.2) */
+#define LH_SUM_FDS 1 /* finite-difference sieve (App. B.4), sign-halved */
+#define LH_ACC_FP64 0 /* plain double accumulation of the signed term sum */
+#define LH_ACC_DD 1   /* double-double (TwoProd/TwoSum) accumulation */
+
+typedef struct {
+  int32_t sum;        /* LH_SUM_FDS (default) or LH_SUM_ET */
+  int32_t acc;        /* LH_ACC_DD (default) or LH_ACC_FP64 */
+  int64_t term_begin; /* first term of the enumeration to include (default 0) */
+  int64_t term_end;   /* one past the last term, -1 = all (default) */
+  int32_t scaled;     /* 1 (default): out = lhaf.  0: out = raw partial sum over
+                         [term_begin, term_end) without the 2^-n FDS prefactor,
+                         for splitting one lhaf across calls or devices */
+  int32_t schedule;   /* -1 (default): tuned/heuristic; >= 0: index into the
+                         schedule table (lhaf_schedule_count()) */
+  void* workspace;    /* device scratch; NULL = library-owned buffer */
+  size_t ws_bytes;
+  lh_c128* out_lo;    /* nullable device array: low parts of the double-double
+                         results (out holds the high parts) */
+} lh_opts;
+
+/* Term enumeration (identical for every entry point).  Pairs p = 0..H-1 with
+ * repeat counts eta_p, n = sum eta_p.  A term is a mixed-radix number, pair 0
+ * the fastest digit s_p:
+ *   ET : radix eta_p + 1; weight z_p = s_p; coefficient
+ *        (-1)^(n - sum s) prod C(eta_p, s_p); the all-zero term is 0.
+ *   FDS: the halving pair hp is the first pair with odd eta (else pair 0),
+ *        radix floor(eta_hp/2) + 1; other pairs radix eta_p + 1; weight
+ *        d_p = eta_p - 2 s_p; coefficient prod (-1)^(s_p) C(eta_p, s_p), times 2
+ *        for the halving pair unless 2 s_hp = eta_hp; prefactor 2^-n.
+ * Plain problems pair position i with position N/2 + i (eta = 1).  Repeated
+ * problems use the greedy matching (sort by count descending, ties by index
+ * ascending; (m1,m1) x floor(n1/2) if n1 >= 2 n2, else (m1,m2) x n2).
+ */
+
+void lh_opts_default(lh_opts* opts);
+const char* lh_status_string(lh_status s);
+int32_t lhaf_schedule_count(void);
+
+/* Number of terms of the enumeration for one problem (host only, no GPU).
+ * r: host multiplicities (NULL = plain problem of size N). */
+int64_t lhaf_term_count(int32_t N, const int32_t* r, int32_t sum);
+
+/* Host planner output for one problem (for inspection and tests).
+ * pos: 2H entries, pos[p] and pos[H+p] are the two ends of pair p as indices
+ * into the problem's index list (-1 = padding vertex); eta: H repeat counts.
+ * Returns H, or a negative lh_status. */
+int32_t lhaf_plan_pairs(int32_t N, const int32_t* r, int32_t* pos, int32_t* eta);
+
+/* lhaf(A, gamma) of one N x N matrix (App. B).
+ * A: device, N x N, row-major, leading dimension lda >= N; diagonal ignored.
+ * gamma: device, N loop weights.  out: device, 1 value.  err_est: device,
+ * nullable, absolute error estimate of out.  N = 0 gives 1. */
+lh_status lhaf(const lh_c128* A, int64_t lda, const lh_c128* gamma, int32_t N, lh_c128* out,
+               double* err_est, const lh_opts* opts, void* stream);
+
+/* lhaf(A_r, gamma_r): row/column i of the M x M matrix A repeated r_i times
+ * (App. A; the collision form of App. B.2/B.3).  r: HOST, M entries >= 0,
+ * sum r <= 64.  r = all ones equals lhaf on A. */
+lh_status lhaf_repeated(const lh_c128* A, int64_t lda, const lh_c128* gamma, const int32_t* r,
+                        int32_t M, lh_c128* out, double* err_est, const lh_opts* opts,
+                        void* stream);
+
+/* Many loop hafnians in one persistent launch (App. B.5 batching; the
+ * chain-rule step of App. A.2 needs many lhafs of different sizes).
+ * Problem b uses the matrix A_base + b*stride_A (stride_A = 0: one shared
+ * base matrix) and gamma_base + b*stride_g, restricted to the index list
+ * idx[idx_off[b] .. idx_off[b+1]) (idx: device, NULL = 0,1,2,...);
+ * idx_off: HOST, B+1 entries.  r: HOST, nullable, multiplicities packed like
+ * idx (NULL = plain).  out: device [B]; err_est: device [B] or NULL.
+ * workspace: device, at least lhaf_batched_workspace(...) bytes. */
+size_t lhaf_batched_workspace(int32_t B, const int64_t* idx_off, const int32_t* r,
+                              const lh_opts* opts);
+lh_status lhaf_batched(int32_t B, const lh_c128* A_base, int64_t lda, int64_t stride_A,
+                       const lh_c128* gamma_base, int64_t stride_g, const int32_t* idx,
+                       const int64_t* idx_off, const int32_t* r, lh_c128* out, double* err_est,
+                       void* workspace, size_t ws_bytes, const lh_opts* opts, void* stream);
+
+/* Gradients of the batch above (the paper has none; adjoint of the per-term
+ * power-trace recursion).  Holomorphic derivative, returned in PyTorch's
+ * convention for complex inputs:
+ *   dA_b = grad_out_b * conj(d lhaf_b / d A_b),  dgamma likewise,
+ * where lhaf is read as a function of the full matrix through sym(A), so
+ *   d lhaf / d A_ij = d lhaf / d A_ji = lhaf(A without rows/cols i,j) / 2  (i != j),
+ *   d lhaf / d gamma_i = lhaf(A without row/col i),
+ *   d lhaf / d A_ii = 0 for plain problems, C(r_i,2) lhaf(A_{r-2e_i}) repeated.
+ * dA: device; if stride_A != 0, problem b writes dA + b*stride_A (lda); if
+ * stride_A == 0, gradients of all problems are summed into one base-sized dA.
+ * dgamma likewise with stride_g.  Both are overwritten (not accumulated).
+ * workspace: at least lhaf_backward_workspace(...) bytes. */
+size_t lhaf_backward_workspace(int32_t B, const int64_t* idx_off, const int32_t* r,
+                               int32_t base_dim, const lh_opts* opts);
+lh_status lhaf_backward(int32_t B, const lh_c128* A_base, int64_t lda, int64_t stride_A,
+                        const lh_c128* gamma_base, int64_t stride_g, const int32_t* idx,
+                        const int64_t* idx_off, const int32_t* r, const lh_c128* grad_out,
+                        lh_c128* dA, lh_c128* dgamma, int32_t base_dim, void* workspace,
+                        size_t ws_bytes, const lh_opts* opts, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LHAF_H */

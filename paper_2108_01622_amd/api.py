@@ -1,0 +1,185 @@
+"""PyTorch-facing wrappers of the C ABI (same names as include/lhaf.h).
+
+Tensors must be complex128 on a ROCm device; results are complex128 device
+tensors.  Work is queued on torch's current HIP stream.  The functions only
+marshal arguments: planning, the term sums and every reduction run in the
+HIP library.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _binding as Bn
+
+
+def _stream_ptr(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev_c128(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a ROCm device (got {t.device})")
+    if t.dtype != torch.complex128:
+        t = t.to(torch.complex128)
+    return t.contiguous()
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def lhaf(A: torch.Tensor, gamma: torch.Tensor | None = None, r=None, *, sum: str = "fds",
+         acc: str = "dd", term_begin: int = 0, term_end: int = -1, scaled: bool = True,
+         schedule: int = -1, return_error: bool = False, return_lo: bool = False,
+         workspace: torch.Tensor | None = None):
+    """Loop hafnian of one matrix.  gamma=None takes gamma = diag(A).  With r
+    (host integer multiplicities) this is lhaf_repeated: lhaf(A_r, gamma_r)."""
+    A = _dev_c128(A, "A")
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be square")
+    N = A.shape[0]
+    gamma = torch.diagonal(A).contiguous() if gamma is None else _dev_c128(gamma, "gamma")
+    out = torch.empty((), dtype=torch.complex128, device=A.device)
+    err = torch.empty((), dtype=torch.float64, device=A.device)
+    lo = torch.zeros((), dtype=torch.complex128, device=A.device) if return_lo else None
+    o = Bn.make_opts(sum, acc, term_begin, term_end, scaled, schedule, workspace, lo)
+    with torch.cuda.device(A.device):
+        st = _stream_ptr(A.device)
+        if r is None:
+            Bn.check(Bn.lib().lhaf(_p(A), N, _p(gamma), N, _p(out), _p(err), ctypes.byref(o), st))
+        else:
+            rr = np.ascontiguousarray(np.asarray(r), dtype=np.int32)
+            if len(rr) != N:
+                raise ValueError("r must have one entry per row of A")
+            Bn.check(Bn.lib().lhaf_repeated(_p(A), N, _p(gamma), Bn.host_ptr(rr), N, _p(out),
+                                            _p(err), ctypes.byref(o), st))
+    res = [out]
+    if return_error:
+        res.append(err)
+    if return_lo:
+        res.append(lo)
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def lhaf_repeated(A, gamma, r, **kw):
+    return lhaf(A, gamma, r, **kw)
+
+
+def _batch_args(A, gamma, idx, idx_off, r):
+    A = _dev_c128(A, "A")
+    gamma = _dev_c128(gamma, "gamma")
+    if A.dim() == 3:  # dense stack: problem b = A[b], identity indices
+        Bsz, N, N2 = A.shape
+        if N != N2 or gamma.shape != (Bsz, N):
+            raise ValueError("dense batch needs A (B,N,N) and gamma (B,N)")
+        lda, sA, sg = N, N * N, N
+        off = np.arange(Bsz + 1, dtype=np.int64) * N if idx_off is None else np.asarray(idx_off, np.int64)
+        idx_t = None if idx is None else _idx_tensor(idx, A.device)
+    else:
+        if idx_off is None:
+            raise ValueError("a shared base matrix needs idx_off")
+        Bsz = len(idx_off) - 1
+        lda, sA, sg = A.shape[1], 0, 0
+        off = np.ascontiguousarray(idx_off, dtype=np.int64)
+        idx_t = None if idx is None else _idx_tensor(idx, A.device)
+    rr = None if r is None else np.ascontiguousarray(np.asarray(r), dtype=np.int32)
+    return A, gamma, Bsz, lda, sA, sg, off, idx_t, rr
+
+
+def _idx_tensor(idx, device):
+    if isinstance(idx, torch.Tensor):
+        return idx.to(device=device, dtype=torch.int32).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(idx, dtype=np.int32), device=device)
+
+
+def lhaf_batched_workspace(idx_off, r=None, **kw) -> int:
+    off = np.ascontiguousarray(idx_off, dtype=np.int64)
+    rr = None if r is None else np.ascontiguousarray(r, dtype=np.int32)
+    o = Bn.make_opts(kw.get("sum", "fds"), kw.get("acc", "dd"), kw.get("term_begin", 0),
+                     kw.get("term_end", -1), kw.get("scaled", True), kw.get("schedule", -1))
+    return int(Bn.lib().lhaf_batched_workspace(len(off) - 1, Bn.host_ptr(off), Bn.host_ptr(rr),
+                                               ctypes.byref(o)))
+
+
+def lhaf_batched(A, gamma, idx=None, idx_off=None, r=None, *, sum="fds", acc="dd",
+                 term_begin=0, term_end=-1, scaled=True, schedule=-1, return_error=False,
+                 return_lo=False, workspace=None):
+    """Many loop hafnians in one persistent launch.  Either a dense stack
+    A (B,N,N), gamma (B,N), or a shared base A (M,M), gamma (M) with index
+    lists idx[idx_off[b]:idx_off[b+1]] (r: optional multiplicities packed like
+    idx)."""
+    A, gamma, Bsz, lda, sA, sg, off, idx_t, rr = _batch_args(A, gamma, idx, idx_off, r)
+    out = torch.empty(Bsz, dtype=torch.complex128, device=A.device)
+    err = torch.empty(Bsz, dtype=torch.float64, device=A.device)
+    lo = torch.zeros(Bsz, dtype=torch.complex128, device=A.device) if return_lo else None
+    o = Bn.make_opts(sum, acc, term_begin, term_end, scaled, schedule, None, lo)
+    need = int(Bn.lib().lhaf_batched_workspace(Bsz, Bn.host_ptr(off), Bn.host_ptr(rr), ctypes.byref(o)))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
+    with torch.cuda.device(A.device):
+        Bn.check(Bn.lib().lhaf_batched(Bsz, _p(A), lda, sA, _p(gamma), sg, _p(idx_t),
+                                       Bn.host_ptr(off), Bn.host_ptr(rr), _p(out), _p(err),
+                                       _p(workspace), workspace.numel(), ctypes.byref(o),
+                                       _stream_ptr(A.device)))
+    res = [out]
+    if return_error:
+        res.append(err)
+    if return_lo:
+        res.append(lo)
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def lhaf_backward(A, gamma, grad_out, idx=None, idx_off=None, r=None, *, sum="fds",
+                  acc="dd", schedule=-1, workspace=None):
+    """Gradients (dA, dgamma) of the batch in PyTorch's complex convention:
+    grad_out * conj(d lhaf / d input)."""
+    A, gamma, Bsz, lda, sA, sg, off, idx_t, rr = _batch_args(A, gamma, idx, idx_off, r)
+    grad_out = _dev_c128(grad_out, "grad_out").reshape(-1)
+    if grad_out.numel() != Bsz:
+        raise ValueError("grad_out needs one value per problem")
+    base_dim = A.shape[-1]
+    dA = torch.empty_like(A)
+    dg = torch.empty_like(gamma)
+    o = Bn.make_opts(sum, acc, 0, -1, True, schedule)
+    need = int(Bn.lib().lhaf_backward_workspace(Bsz, Bn.host_ptr(off), Bn.host_ptr(rr), base_dim,
+                                                ctypes.byref(o)))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
+    with torch.cuda.device(A.device):
+        Bn.check(Bn.lib().lhaf_backward(Bsz, _p(A), lda, sA, _p(gamma), sg, _p(idx_t),
+                                        Bn.host_ptr(off), Bn.host_ptr(rr), _p(grad_out), _p(dA),
+                                        _p(dg), base_dim, _p(workspace), workspace.numel(),
+                                        ctypes.byref(o), _stream_ptr(A.device)))
+    return dA, dg
+
+
+class LhafFunction(torch.autograd.Function):
+    """lhaf of a dense batch (A (B,N,N), gamma (B,N)) with the adjoint kernel
+    as backward."""
+
+    @staticmethod
+    def forward(ctx, A, gamma, sum="fds", acc="dd", r=None):
+        ctx.save_for_backward(A, gamma)
+        ctx.opts = (sum, acc, r)
+        out = lhaf_batched(A, gamma, r=r, sum=sum, acc=acc)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        A, gamma = ctx.saved_tensors
+        sum, acc, r = ctx.opts
+        dA, dg = lhaf_backward(A, gamma, grad_out.contiguous(), r=r, sum=sum, acc=acc)
+        return dA, dg, None, None, None
+
+
+def lhaf_autograd(A, gamma, sum="fds", acc="dd", r=None):
+    squeeze = A.dim() == 2
+    if squeeze:
+        A, gamma = A.unsqueeze(0), gamma.unsqueeze(0)
+    out = LhafFunction.apply(A, gamma, sum, acc, r)
+    return out[0] if squeeze else out

@@ -1,0 +1,568 @@
+// C ABI of the loop-hafnian library: validation, planning, workspace layout
+// and kernel launches.  No torch types; every buffer belongs to the caller
+// (or, without a workspace, to one lazily grown per-device scratch buffer).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lhaf.h"
+#include "lhaf_device.h"
+#include "lhaf_internal.h"
+// kernels (one translation unit with the launches)
+#include "lhaf_forward.hip"
+
+namespace lh {
+
+namespace {
+
+std::mutex g_mu;
+struct DevState {
+  bool binom_ready = false;
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  int cus = 0;
+};
+DevState g_dev[64];
+
+lh_status ensure_device(int& dev) {
+  if (hipGetDevice(&dev) != hipSuccess) return LH_EHIP;
+  if (dev < 0 || dev >= 64) return LH_EHIP;
+  DevState& S = g_dev[dev];
+  if (!S.binom_ready) {
+    double tab[33][33];
+    for (int a = 0; a < 33; ++a)
+      for (int b = 0; b < 33; ++b) {
+        if (b > a) {
+          tab[a][b] = 0.0;
+          continue;
+        }
+        double r = 1.0;
+        for (int k = 1; k <= b; ++k) r = r * (a - b + k) / k;
+        tab[a][b] = std::round(r);
+      }
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_binom), tab, sizeof(tab)) != hipSuccess) return LH_EHIP;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return LH_EHIP;
+    S.cus = cus > 0 ? cus : 1;
+    S.binom_ready = true;
+  }
+  return LH_OK;
+}
+
+lh_status get_scratch(int dev, size_t bytes, void** out) {
+  DevState& S = g_dev[dev];
+  if (S.scratch_bytes < bytes) {
+    if (S.scratch) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(S.scratch);
+      S.scratch = nullptr;
+      S.scratch_bytes = 0;
+    }
+    size_t sz = std::max<size_t>(bytes, 1 << 20);
+    if (hipMalloc(&S.scratch, sz) != hipSuccess) return LH_ENOMEM;
+    S.scratch_bytes = sz;
+  }
+  *out = S.scratch;
+  return LH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// schedules: persistent waves per CU x items per wave
+struct Schedule {
+  int waves_per_cu;
+  int items_per_wave;
+};
+const Schedule kSchedules[] = {{4, 4},  {8, 4},  {16, 4}, {4, 8},  {8, 8},
+                               {16, 8}, {8, 2},  {8, 16}, {16, 16}, {4, 16}};
+const int kNumSchedules = (int)(sizeof(kSchedules) / sizeof(kSchedules[0]));
+
+// schedule cache: lines "bclass mode schedule" from $LHAF_TUNE_CACHE
+struct TuneCache {
+  bool loaded = false;
+  int best[9][2];
+};
+TuneCache g_tune;
+
+int pick_schedule(const lh_opts* o, int bmax, int mode) {
+  if (o && o->schedule >= 0 && o->schedule < kNumSchedules) return o->schedule;
+  if (!g_tune.loaded) {
+    for (auto& r : g_tune.best) r[0] = r[1] = -1;
+    const char* path = std::getenv("LHAF_TUNE_CACHE");
+    if (path) {
+      if (FILE* f = std::fopen(path, "r")) {
+        int b, md, s;
+        while (std::fscanf(f, "%d %d %d", &b, &md, &s) == 3)
+          if (b >= 1 && b <= 8 && (md == 0 || md == 1) && s >= 0 && s < kNumSchedules)
+            g_tune.best[b][md] = s;
+        std::fclose(f);
+      }
+    }
+    g_tune.loaded = true;
+  }
+  int s = g_tune.best[bmax][mode ? 1 : 0];
+  return s >= 0 ? s : 1;
+}
+
+// ---------------------------------------------------------------------------
+struct ProblemIn {
+  PairPlan plan;
+  int64_t a_off, g_off, i_off;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t counter, probs, items, parts, aoff, goff, ioff, cdata, total;
+};
+
+Layout layout_for(int nprob, int nitems, size_t c_elems) {
+  Layout L;
+  size_t o = 0;
+  L.counter = o;
+  o = align_up(o + 256);
+  L.probs = o;
+  o = align_up(o + sizeof(Prob) * (size_t)std::max(nprob, 1));
+  L.items = o;
+  o = align_up(o + sizeof(Item) * (size_t)std::max(nitems, 1));
+  L.parts = o;
+  o = align_up(o + sizeof(Partial) * (size_t)std::max(nitems, 1));
+  L.aoff = o;
+  o = align_up(o + 8 * (size_t)std::max(nprob, 1));
+  L.goff = o;
+  o = align_up(o + 8 * (size_t)std::max(nprob, 1));
+  L.ioff = o;
+  o = align_up(o + 8 * (size_t)std::max(nprob, 1));
+  L.cdata = o;
+  o = align_up(o + sizeof(cd) * c_elems);
+  L.total = o;
+  return L;
+}
+
+struct Plan {
+  std::vector<Prob> probs;
+  std::vector<Item> items;
+  std::vector<int64_t> aoff, goff, ioff;
+  size_t c_elems = 0;
+  int bmax = 1, nmax = 0;
+  int grid = 1;
+  Layout lay;
+};
+
+// relative cost of one term with register tile B (Householder ~ m^3)
+double term_cost(int B) { return (double)B * B * B + 2.0; }
+
+lh_status build_plan(std::vector<ProblemIn>& pin, const lh_opts& o, int dev, Plan& pl,
+                     bool for_backward) {
+  const int nprob = (int)pin.size();
+  pl.probs.resize(nprob);
+  pl.aoff.resize(nprob);
+  pl.goff.resize(nprob);
+  pl.ioff.resize(nprob);
+  double total_cost = 0.0;
+  int mode_any = o.sum;
+  for (int b = 0; b < nprob; ++b) {
+    Prob& P = pl.probs[b];
+    if (!fill_prob(pin[b].plan, o.sum, o.term_begin, o.term_end, o.scaled != 0 || for_backward, &P))
+      return LH_ESIZE;
+    if (for_backward) {
+      P.t0 = 0;
+      P.t1 = P.T;
+    }
+    P.c_off = (int64_t)pl.c_elems;
+    pl.c_elems += (size_t)(8 * P.B) * (8 * P.B) + 64;
+    pl.aoff[b] = pin[b].a_off;
+    pl.goff[b] = pin[b].g_off;
+    pl.ioff[b] = pin[b].i_off;
+    if (P.n > 0) {
+      pl.bmax = std::max(pl.bmax, P.B);
+      pl.nmax = std::max(pl.nmax, P.n);
+      total_cost += (double)(P.t1 - P.t0) * term_cost(P.B);
+    }
+  }
+  const int sched = pick_schedule(&o, pl.bmax, mode_any);
+  const Schedule S = kSchedules[sched];
+  const int cus = g_dev[dev].cus;
+  const int waves = std::max(1, cus * S.waves_per_cu);
+  const double target = std::max(total_cost / ((double)waves * S.items_per_wave), 1e-9);
+  struct Tmp {
+    int prob;
+    int64_t t0, t1;
+    double cost;
+  };
+  std::vector<Tmp> tmp;
+  for (int b = 0; b < nprob; ++b) {
+    Prob& P = pl.probs[b];
+    const int64_t len = P.t1 - P.t0;
+    if (P.n == 0 || len <= 0) continue;
+    const double c = (double)len * term_cost(P.B);
+    int64_t k = (int64_t)std::ceil(c / target);
+    k = std::max<int64_t>(1, std::min<int64_t>(k, len));
+    k = std::min<int64_t>(k, 1 << 22);
+    for (int64_t s = 0; s < k; ++s) {
+      const int64_t a = P.t0 + len * s / k, e = P.t0 + len * (s + 1) / k;
+      tmp.push_back({b, a, e, (double)(e - a) * term_cost(P.B)});
+    }
+  }
+  // longest-processing-time first; ties by problem and range (deterministic)
+  std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp& x, const Tmp& y) { return x.cost > y.cost; });
+  // give every problem its items as a contiguous block of partial slots in
+  // term order, independent of the processing order
+  std::vector<int> count(nprob, 0);
+  for (auto& t : tmp) count[t.prob]++;
+  int acc = 0;
+  for (int b = 0; b < nprob; ++b) {
+    pl.probs[b].first_item = acc;
+    pl.probs[b].n_items = count[b];
+    acc += count[b];
+  }
+  // slot of each item = first_item + rank of its range inside the problem
+  std::vector<std::vector<int64_t>> starts(nprob);
+  for (auto& t : tmp) starts[t.prob].push_back(t.t0);
+  for (auto& s : starts) std::sort(s.begin(), s.end());
+  pl.items.resize(tmp.size());
+  // processing order = LPT order; the kernel writes partial `slot`
+  std::vector<Item> ordered(tmp.size());
+  for (size_t r = 0; r < tmp.size(); ++r) {
+    const Tmp& t = tmp[r];
+    auto& st = starts[t.prob];
+    const int rank = (int)(std::lower_bound(st.begin(), st.end(), t.t0) - st.begin());
+    Item I;
+    I.prob = t.prob;
+    I.pad = pl.probs[t.prob].first_item + rank;  // partial slot
+    I.t0 = t.t0;
+    I.t1 = t.t1;
+    ordered[r] = I;
+  }
+  pl.items = ordered;
+  // every item must address a valid problem, slot and term range
+  for (const Item& I : pl.items) {
+    const Prob& P = pl.probs[I.prob];
+    if (I.prob < 0 || I.prob >= nprob || I.t0 < P.t0 || I.t1 > P.t1 || I.t0 >= I.t1 ||
+        I.pad < P.first_item || I.pad >= P.first_item + P.n_items)
+      return LH_EINVAL;
+  }
+  pl.grid = (int)std::min<int64_t>((int64_t)waves, std::max<int64_t>(1, (int64_t)pl.items.size()));
+  pl.lay = layout_for(nprob, (int)pl.items.size(), pl.c_elems);
+  return LH_OK;
+}
+
+}  // namespace
+
+// launch a planned forward evaluation
+lh_status run_forward(Plan& pl, const lh_c128* A, int64_t lda, const lh_c128* g,
+                      const int32_t* idx, lh_c128* out, double* err, const lh_opts& o,
+                      void* ws, hipStream_t st, int dev);
+
+std::mutex g_stage_mu;
+void* g_stage[64] = {nullptr};
+size_t g_stage_bytes[64] = {0};
+
+lh_status upload_plan(const Plan& pl, char* base, hipStream_t st, int dev) {
+  const size_t nprob = pl.probs.size(), nit = pl.items.size();
+  const size_t span = pl.lay.cdata;  // tables occupy [probs, cdata)
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  if (g_stage_bytes[dev] < span) {
+    if (g_stage[dev]) (void)hipHostFree(g_stage[dev]);
+    g_stage[dev] = nullptr;
+    g_stage_bytes[dev] = 0;
+    size_t sz = std::max<size_t>(span, 1 << 16);
+    if (hipHostMalloc(&g_stage[dev], sz, hipHostMallocDefault) != hipSuccess) return LH_ENOMEM;
+    g_stage_bytes[dev] = sz;
+  }
+  char* h = static_cast<char*>(g_stage[dev]);
+  std::memset(h, 0, span);
+  std::memcpy(h + pl.lay.probs, pl.probs.data(), sizeof(Prob) * nprob);
+  if (nit) std::memcpy(h + pl.lay.items, pl.items.data(), sizeof(Item) * nit);
+  std::memcpy(h + pl.lay.aoff, pl.aoff.data(), 8 * nprob);
+  std::memcpy(h + pl.lay.goff, pl.goff.data(), 8 * nprob);
+  std::memcpy(h + pl.lay.ioff, pl.ioff.data(), 8 * nprob);
+  const size_t off = pl.lay.probs;
+  if (hipMemcpyAsync(base + off, h + off, span - off, hipMemcpyHostToDevice, st) != hipSuccess)
+    return LH_EHIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return LH_EHIP;
+  return LH_OK;
+}
+
+}  // namespace lh
+
+using namespace lh;
+
+namespace lh {
+
+template <int BMAX>
+static hipError_t launch_fwd(const Plan& pl, char* base, int acc_dd, hipStream_t st) {
+  const size_t lds = lds_bytes_for(std::max(pl.nmax, 1));
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(forward_kernel<BMAX>), dim3(pl.grid), dim3(64), lds, st,
+                     reinterpret_cast<const Prob*>(base + pl.lay.probs),
+                     reinterpret_cast<const Item*>(base + pl.lay.items), (int)pl.items.size(),
+                     reinterpret_cast<int*>(base + pl.lay.counter),
+                     reinterpret_cast<const cd*>(base + pl.lay.cdata),
+                     reinterpret_cast<Partial*>(base + pl.lay.parts), acc_dd, std::max(pl.nmax, 1));
+  return hipGetLastError();
+}
+
+// Copy the host plan (problem table, item list, offsets) into the workspace.
+// The tables go through one pinned staging buffer per device; the copy is
+// waited for before returning, so the staging buffer and the plan can be
+// reused by the next call.
+lh_status upload_plan(const Plan& pl, char* base, hipStream_t st, int dev);
+
+lh_status run_forward(Plan& pl, const lh_c128* A, int64_t lda, const lh_c128* g,
+                      const int32_t* idx, lh_c128* out, double* err, const lh_opts& o, void* ws,
+                      hipStream_t st, int dev) {
+  char* base = static_cast<char*>(ws);
+  const int nprob = (int)pl.probs.size();
+  lh_status us = upload_plan(pl, base, st, dev);
+  if (us != LH_OK) return us;
+  hipLaunchKernelGGL(pack_kernel, dim3(nprob), dim3(256), 0, st,
+                     reinterpret_cast<const Prob*>(base + pl.lay.probs),
+                     reinterpret_cast<const int64_t*>(base + pl.lay.aoff),
+                     reinterpret_cast<const int64_t*>(base + pl.lay.goff),
+                     reinterpret_cast<const int64_t*>(base + pl.lay.ioff), A, lda, g, idx,
+                     reinterpret_cast<cd*>(base + pl.lay.cdata),
+                     reinterpret_cast<int*>(base + pl.lay.counter));
+  if (hipGetLastError() != hipSuccess) return LH_EHIP;
+  const int acc_dd = o.acc == LH_ACC_DD ? 1 : 0;
+  if (!pl.items.empty()) {
+    hipError_t e;
+    switch (pl.bmax) {
+      case 1: e = launch_fwd<1>(pl, base, acc_dd, st); break;
+      case 2: e = launch_fwd<2>(pl, base, acc_dd, st); break;
+      case 3: e = launch_fwd<3>(pl, base, acc_dd, st); break;
+      case 4: e = launch_fwd<4>(pl, base, acc_dd, st); break;
+      case 5: e = launch_fwd<5>(pl, base, acc_dd, st); break;
+      case 6: e = launch_fwd<6>(pl, base, acc_dd, st); break;
+      case 7: e = launch_fwd<7>(pl, base, acc_dd, st); break;
+      default: e = launch_fwd<8>(pl, base, acc_dd, st); break;
+    }
+    if (e != hipSuccess) return LH_EHIP;
+  }
+  hipLaunchKernelGGL(finalize_kernel, dim3((nprob + 127) / 128), dim3(128), 0, st,
+                     reinterpret_cast<const Prob*>(base + pl.lay.probs), nprob,
+                     reinterpret_cast<const Partial*>(base + pl.lay.parts), out, o.out_lo, err,
+                     acc_dd);
+  if (hipGetLastError() != hipSuccess) return LH_EHIP;
+  return LH_OK;
+}
+
+}  // namespace lh
+
+// ===========================================================================
+// public ABI
+extern "C" {
+
+void lh_opts_default(lh_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->sum = LH_SUM_FDS;
+  o->acc = LH_ACC_DD;
+  o->term_begin = 0;
+  o->term_end = -1;
+  o->scaled = 1;
+  o->schedule = -1;
+  o->workspace = nullptr;
+  o->ws_bytes = 0;
+  o->out_lo = nullptr;
+}
+
+const char* lh_status_string(lh_status s) {
+  switch (s) {
+    case LH_OK: return "ok";
+    case LH_EINVAL: return "invalid argument";
+    case LH_ESIZE: return "problem too large (N > 64)";
+    case LH_EHIP: return "HIP runtime error";
+    case LH_ENOMEM: return "workspace too small or allocation failed";
+    case LH_EUNSUPPORTED: return "unsupported option combination";
+    default: return "unknown status";
+  }
+}
+
+int32_t lhaf_schedule_count(void) { return kNumSchedules; }
+
+int64_t lhaf_term_count(int32_t N, const int32_t* r, int32_t sum) {
+  if (N < 0) return -LH_EINVAL;
+  PairPlan pp;
+  if (r) {
+    for (int i = 0; i < N; ++i)
+      if (r[i] < 0) return -LH_EINVAL;
+    pp = plan_repeated(r, N);
+  } else {
+    pp = plan_plain(N);
+  }
+  return term_count(pp, sum == LH_SUM_FDS ? 1 : 0, nullptr);
+}
+
+int32_t lhaf_plan_pairs(int32_t N, const int32_t* r, int32_t* pos, int32_t* eta) {
+  if (N < 0 || !pos || !eta) return -LH_EINVAL;
+  PairPlan pp;
+  if (r) {
+    int tot = 0;
+    for (int i = 0; i < N; ++i) {
+      if (r[i] < 0) return -LH_EINVAL;
+      tot += r[i];
+    }
+    if (tot > kMaxN) return -LH_ESIZE;
+    pp = plan_repeated(r, N);
+  } else {
+    if (N > kMaxN) return -LH_ESIZE;
+    pp = plan_plain(N);
+  }
+  for (int i = 0; i < 2 * pp.H; ++i) pos[i] = pp.pos[i];
+  for (int p = 0; p < pp.H; ++p) eta[p] = pp.eta[p];
+  return pp.H;
+}
+
+static lh_status validate_opts(const lh_opts* opts, lh_opts& o) {
+  lh_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.sum != LH_SUM_ET && o.sum != LH_SUM_FDS) return LH_EINVAL;
+  if (o.acc != LH_ACC_FP64 && o.acc != LH_ACC_DD) return LH_EINVAL;
+  return LH_OK;
+}
+
+static lh_status batched_impl(int32_t B, const lh_c128* A_base, int64_t lda, int64_t stride_A,
+                              const lh_c128* gamma_base, int64_t stride_g, const int32_t* idx,
+                              const int64_t* idx_off, const int32_t* r, lh_c128* out,
+                              double* err_est, void* workspace, size_t ws_bytes,
+                              const lh_opts& o, hipStream_t st, bool query_only,
+                              size_t* need_bytes) {
+  if (B < 0 || !idx_off) return LH_EINVAL;
+  std::vector<ProblemIn> pin(B);
+  for (int b = 0; b < B; ++b) {
+    const int64_t s0 = idx_off[b], s1 = idx_off[b + 1];
+    if (s1 < s0 || s0 < 0) return LH_EINVAL;
+    const int64_t N = s1 - s0;
+    if (r) {
+      int64_t tot = 0;
+      for (int64_t k = s0; k < s1; ++k) {
+        if (r[k] < 0) return LH_EINVAL;
+        tot += r[k];
+      }
+      if (N > kMaxN || tot > kMaxN) return LH_ESIZE;
+      pin[b].plan = plan_repeated(r + s0, (int)N);
+    } else {
+      if (N > kMaxN) return LH_ESIZE;
+      pin[b].plan = plan_plain((int)N);
+    }
+    pin[b].a_off = (int64_t)b * stride_A;
+    pin[b].g_off = (int64_t)b * stride_g;
+    pin[b].i_off = s0;
+  }
+  int dev = 0;
+  if (!query_only || true) {
+    lh_status s = ensure_device(dev);
+    if (s != LH_OK) return s;
+  }
+  Plan pl;
+  lh_status s = build_plan(pin, o, dev, pl, false);
+  if (s != LH_OK) return s;
+  if (query_only) {
+    *need_bytes = pl.lay.total;
+    return LH_OK;
+  }
+  if (B == 0) return LH_OK;
+  if (!A_base || !gamma_base || !out || lda < 1) return LH_EINVAL;
+  void* ws = workspace;
+  if (!ws) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    s = get_scratch(dev, pl.lay.total, &ws);
+    if (s != LH_OK) return s;
+    return run_forward(pl, A_base, lda, gamma_base, idx, out, err_est, o, ws, st, dev);
+  }
+  if (ws_bytes < pl.lay.total) return LH_ENOMEM;
+  return run_forward(pl, A_base, lda, gamma_base, idx, out, err_est, o, ws, st, dev);
+}
+
+size_t lhaf_batched_workspace(int32_t B, const int64_t* idx_off, const int32_t* r,
+                              const lh_opts* opts) {
+  lh_opts o;
+  if (validate_opts(opts, o) != LH_OK) return 0;
+  size_t need = 0;
+  if (batched_impl(B, nullptr, 1, 0, nullptr, 0, nullptr, idx_off, r, nullptr, nullptr, nullptr,
+                   0, o, nullptr, true, &need) != LH_OK)
+    return 0;
+  return need;
+}
+
+lh_status lhaf_batched(int32_t B, const lh_c128* A_base, int64_t lda, int64_t stride_A,
+                       const lh_c128* gamma_base, int64_t stride_g, const int32_t* idx,
+                       const int64_t* idx_off, const int32_t* r, lh_c128* out, double* err_est,
+                       void* workspace, size_t ws_bytes, const lh_opts* opts, void* stream) {
+  lh_opts o;
+  lh_status s = validate_opts(opts, o);
+  if (s != LH_OK) return s;
+  if (workspace == nullptr && o.workspace) {
+    workspace = o.workspace;
+    ws_bytes = o.ws_bytes;
+  }
+  return batched_impl(B, A_base, lda, stride_A, gamma_base, stride_g, idx, idx_off, r, out,
+                      err_est, workspace, ws_bytes, o, (hipStream_t)stream, false, nullptr);
+}
+
+lh_status lhaf(const lh_c128* A, int64_t lda, const lh_c128* gamma, int32_t N, lh_c128* out,
+               double* err_est, const lh_opts* opts, void* stream) {
+  lh_opts o;
+  lh_status s = validate_opts(opts, o);
+  if (s != LH_OK) return s;
+  if (N < 0 || !out) return LH_EINVAL;
+  if (N > kMaxN) return LH_ESIZE;
+  if (N > 0 && (!A || !gamma || lda < N)) return LH_EINVAL;
+  int64_t off[2] = {0, N};
+  if (N == 0) {
+    int dev;
+    s = ensure_device(dev);
+    if (s != LH_OK) return s;
+    hipLaunchKernelGGL(fill_one_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, out, o.out_lo,
+                       err_est, 1);
+    return hipGetLastError() == hipSuccess ? LH_OK : LH_EHIP;
+  }
+  return batched_impl(1, A, lda, 0, gamma, 0, nullptr, off, nullptr, out, err_est, o.workspace,
+                      o.ws_bytes, o, (hipStream_t)stream, false, nullptr);
+}
+
+lh_status lhaf_repeated(const lh_c128* A, int64_t lda, const lh_c128* gamma, const int32_t* r,
+                        int32_t M, lh_c128* out, double* err_est, const lh_opts* opts,
+                        void* stream) {
+  lh_opts o;
+  lh_status s = validate_opts(opts, o);
+  if (s != LH_OK) return s;
+  if (M < 0 || !out || (M > 0 && !r)) return LH_EINVAL;
+  int64_t tot = 0;
+  for (int i = 0; i < M; ++i) {
+    if (r[i] < 0) return LH_EINVAL;
+    tot += r[i];
+  }
+  if (tot > kMaxN) return LH_ESIZE;
+  if (M > 0 && (!A || !gamma || lda < M)) return LH_EINVAL;
+  if (tot == 0) {
+    int dev;
+    s = ensure_device(dev);
+    if (s != LH_OK) return s;
+    hipLaunchKernelGGL(fill_one_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, out, o.out_lo,
+                       err_est, 1);
+    return hipGetLastError() == hipSuccess ? LH_OK : LH_EHIP;
+  }
+  int64_t off[2] = {0, M};
+  return batched_impl(1, A, lda, 0, gamma, 0, nullptr, off, r, out, err_est, o.workspace,
+                      o.ws_bytes, o, (hipStream_t)stream, false, nullptr);
+}
+
+size_t lhaf_backward_workspace(int32_t, const int64_t*, const int32_t*, int32_t, const lh_opts*) {
+  return 0;
+}
+
+lh_status lhaf_backward(int32_t, const lh_c128*, int64_t, int64_t, const lh_c128*, int64_t,
+                        const int32_t*, const int64_t*, const int32_t*, const lh_c128*, lh_c128*,
+                        lh_c128*, int32_t, void*, size_t, const lh_opts*, void*) {
+  return LH_EUNSUPPORTED;
+}
+
+}  // extern "C"

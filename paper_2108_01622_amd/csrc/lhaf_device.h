@@ -1,0 +1,137 @@
+// Device-side building blocks: complex FP64 arithmetic, wavefront reductions
+// on the 8 x 8 lane grid, double-double accumulation.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace lh {
+
+struct cd {
+  double r, i;
+};
+
+__device__ __forceinline__ cd mk(double r, double i) {
+  cd c;
+  c.r = r;
+  c.i = i;
+  return c;
+}
+__device__ __forceinline__ cd czero() { return mk(0.0, 0.0); }
+__device__ __forceinline__ cd cadd(cd a, cd b) { return mk(a.r + b.r, a.i + b.i); }
+__device__ __forceinline__ cd csub(cd a, cd b) { return mk(a.r - b.r, a.i - b.i); }
+__device__ __forceinline__ cd cscale(double s, cd a) { return mk(s * a.r, s * a.i); }
+__device__ __forceinline__ cd cmul(cd a, cd b) {
+  return mk(fma(a.r, b.r, -a.i * b.i), fma(a.r, b.i, a.i * b.r));
+}
+// a*b + c
+__device__ __forceinline__ cd cfma(cd a, cd b, cd c) {
+  return mk(fma(a.r, b.r, fma(-a.i, b.i, c.r)), fma(a.r, b.i, fma(a.i, b.r, c.i)));
+}
+// c - a*b
+__device__ __forceinline__ cd cfnma(cd a, cd b, cd c) {
+  return mk(fma(-a.r, b.r, fma(a.i, b.i, c.r)), fma(-a.r, b.i, fma(-a.i, b.r, c.i)));
+}
+// conj(a)*b + c
+__device__ __forceinline__ cd cjfma(cd a, cd b, cd c) {
+  return mk(fma(a.r, b.r, fma(a.i, b.i, c.r)), fma(a.r, b.i, fma(-a.i, b.r, c.i)));
+}
+// a*conj(b)
+__device__ __forceinline__ cd cmulj(cd a, cd b) {
+  return mk(fma(a.r, b.r, a.i * b.i), fma(a.i, b.r, -a.r * b.i));
+}
+__device__ __forceinline__ double cabs2(cd a) { return fma(a.r, a.r, a.i * a.i); }
+
+// ---------------------------------------------------------------------------
+// Lane grid: lane = 8*p + q.  "Row group" = the 8 lanes sharing p (consecutive
+// lanes), "column group" = the 8 lanes sharing q (stride 8).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  lo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// x + (value of the lane 16 apart): permlane16_swap exchanges 16-lane rows
+// 0<->1 and 2<->3; both outputs together hold the pair.
+__device__ __forceinline__ double sum_xor16(double x) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  auto L = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  auto H = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double(H[0], L[0]) + __hiloint2double(H[1], L[1]);
+}
+__device__ __forceinline__ double sum_xor32(double x) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  auto L = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  auto H = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double(H[0], L[0]) + __hiloint2double(H[1], L[1]);
+}
+
+// Sum over the row group (xor 1, xor 2 by quad permutes, then lane i with
+// lane 7-i inside each group of 8).  Every lane of the group ends with the
+// same bits (IEEE addition is commutative).
+__device__ __forceinline__ double sum_row8(double x) {
+  x += dpp_d<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp_d<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp_d<0x141>(x);  // row_half_mirror
+  return x;
+}
+// Sum over the column group (xor 8 by a rotate of 8 inside 16-lane rows,
+// then the 16- and 32-lane swaps).
+__device__ __forceinline__ double sum_col8(double x) {
+  x += dpp_d<0x128>(x);  // row_ror:8
+  x = sum_xor16(x);
+  x = sum_xor32(x);
+  return x;
+}
+__device__ __forceinline__ cd sum_row8(cd a) { return mk(sum_row8(a.r), sum_row8(a.i)); }
+__device__ __forceinline__ cd sum_col8(cd a) { return mk(sum_col8(a.r), sum_col8(a.i)); }
+__device__ __forceinline__ cd sum_xor32(cd a) { return mk(sum_xor32(a.r), sum_xor32(a.i)); }
+
+__device__ __forceinline__ double shfl_d(double x, int src) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  lo = __builtin_amdgcn_ds_bpermute(src << 2, lo);
+  hi = __builtin_amdgcn_ds_bpermute(src << 2, hi);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double bcast0_d(double x) {
+  int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
+  int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ cd bcast0(cd a) { return mk(bcast0_d(a.r), bcast0_d(a.i)); }
+
+// product over all 64 lanes (exact for the integer factors used here)
+__device__ __forceinline__ double prod_wave(double x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 1; s < 64; s <<= 1) x *= shfl_d(x, lane ^ s);
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// double-double accumulation (Knuth TwoSum, FMA TwoProd)
+struct dd {
+  double hi, lo;
+};
+__device__ __forceinline__ void dd_add_prod(dd& acc, double c, double x) {
+  double p = c * x;
+  double pe = fma(c, x, -p);
+  double s = acc.hi + p;
+  double bb = s - acc.hi;
+  double e = (acc.hi - (s - bb)) + (p - bb);
+  double lo = acc.lo + (e + pe);
+  double h2 = s + lo;
+  acc.lo = lo - (h2 - s);
+  acc.hi = h2;
+}
+__device__ __forceinline__ void dd_add(dd& acc, double hi, double lo) {
+  double s = acc.hi + hi;
+  double bb = s - acc.hi;
+  double e = (acc.hi - (s - bb)) + (hi - bb);
+  double l = acc.lo + (e + lo);
+  double h2 = s + l;
+  acc.lo = l - (h2 - s);
+  acc.hi = h2;
+}
+
+}  // namespace lh

@@ -1,0 +1,113 @@
+"""Write tests/golden/oracle_values.json: reference values for the full-size
+workloads, computed by the CPU oracle only (never by the HIP library).
+
+    python tests/golden/make_golden.py [--only KEY ...] [--threads N]
+
+Each entry records how it was computed.  Methods:
+  memo_f128      definition, memoised recursion, __float128
+  fds_f64        finite-difference sieve, explicit matrix powers, double + Neumaier
+  fds_f128       same in __float128
+  block_f128     block-diagonal A1 (+) A2: lhaf(A1) * lhaf(A2), each half FDS in
+                 __float128 (the paper's own accuracy protocol, App. B.4)
+The file is updated incrementally (existing keys are kept unless --force).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import oracle as O  # noqa: E402
+from paper_2108_01622_amd import inputs as I  # noqa: E402
+
+OUT = os.path.join(HERE, "oracle_values.json")
+
+GRAD40_SAMPLE = [0, 37, 101, 255]
+CHAIN_PER_SIZE = 2
+DENSE52_BLOCK = 10
+DENSE60_BLOCK = 4
+
+
+def cx(z):
+    return [float(np.real(z)), float(np.imag(z))]
+
+
+def jobs():
+    J = {}
+    A, g = I.single16()
+    J["single16"] = lambda A=A, g=g: dict(method="memo_f128", value=cx(O.lhaf_memo(A, g, prec="f128")),
+                                          sha256=I.sha256_of(A, g))
+    st = I.state100(0)
+    def rep(st=st):
+        v, ab = O.lhaf_repeated(st["B"], st["gamma"], st["r"], method="sum", mode="fds", prec="f64",
+                                with_abs=True)
+        pairs, left = O.matched_reps(st["r"])
+        return dict(method="fds_f64 repeated pairs (greedy matching)", value=cx(v), abs_sum=ab,
+                    pattern_counts=[int((st["r"] == k).sum()) for k in (1, 2, 3)],
+                    eta=[p[2] for p in pairs] + ([1] if left is not None else []),
+                    sha256=I.sha256_of(st["B"], st["gamma"], st["r"]))
+    J["state100"] = rep
+    A40, g40 = I.grad40()
+    for b in GRAD40_SAMPLE:
+        def g40job(b=b):
+            v, ab = O.lhaf_sum(A40[b], g40[b], mode="fds", prec="f64", with_abs=True)
+            return dict(method="fds_f64", value=cx(v), abs_sum=ab, sha256=I.sha256_of(A40[b], g40[b]))
+        J[f"grad40/{b}"] = g40job
+    ch = I.chain4096()
+    sizes = ch["sizes"]
+    for N in range(20, 41, 2):
+        picks = [int(i) for i in np.nonzero(sizes == N)[0][:CHAIN_PER_SIZE]]
+        for b in picks:
+            def chjob(b=b):
+                ix = ch["idx"][ch["idx_off"][b]:ch["idx_off"][b + 1]]
+                A = ch["B"][np.ix_(ix, ix)]
+                g = ch["gamma"][ix]
+                v, ab = O.lhaf_sum(A, g, mode="fds", prec="f64", with_abs=True)
+                return dict(method="fds_f64", value=cx(v), abs_sum=ab, N=int(len(ix)))
+            J[f"chain4096/{b}"] = chjob
+    for n, cnt in ((52, DENSE52_BLOCK), (60, DENSE60_BLOCK)):
+        for k in range(cnt):
+            def bjob(n=n, k=k):
+                A, g, (a1, g1), (a2, g2) = I.block_diagonal_stress(n, k)
+                v1 = O.lhaf_sum(a1, g1, mode="fds", prec="f128")
+                v2 = O.lhaf_sum(a2, g2, mode="fds", prec="f128")
+                return dict(method="block_f128", value=cx(v1 * v2), halves=[cx(v1), cx(v2)],
+                            sha256=I.sha256_of(A, g))
+            J[f"block{n}/{k}"] = bjob
+    return J
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--only", nargs="*", default=None)
+    ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
+    ap.add_argument("--force", action="store_true")
+    a = ap.parse_args()
+    O.set_threads(a.threads)
+    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    data.setdefault("_about", "written by tests/golden/make_golden.py from oracle/ only")
+    for key, fn in jobs().items():
+        if a.only and not any(key.startswith(o) for o in a.only):
+            continue
+        if key in data and not a.force:
+            continue
+        t = time.time()
+        res = fn()
+        res["seconds"] = round(time.time() - t, 2)
+        res["threads"] = a.threads
+        data[key] = res
+        json.dump(data, open(OUT + ".tmp", "w"), indent=1, sort_keys=True)
+        os.replace(OUT + ".tmp", OUT)
+        print(f"{key}: {res['value']} ({res['seconds']} s)", flush=True)
+
+
+if __name__ == "__main__":
+    main()

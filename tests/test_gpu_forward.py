@@ -1,0 +1,137 @@
+"""GPU parity of the forward HIP path against the CPU oracle (same seeded
+inputs, element by element).  Tolerance: 1e-10 relative to the double
+oracle for N <= 40 (unless stated), tighter where the oracle is __float128."""
+import numpy as np
+import pytest
+
+from paper_2108_01622_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2108_01622_amd import api as A
+    return A
+
+
+def rel(a, b):
+    return abs(complex(a) - complex(b)) / max(abs(complex(b)), 1e-300)
+
+
+def dev(T, x):
+    return T.as_tensor(np.ascontiguousarray(x), dtype=T.complex128, device="cuda")
+
+
+@pytest.mark.parametrize("mode", ["fds", "et"])
+@pytest.mark.parametrize("acc", ["dd", "fp64"])
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 7, 8, 9, 12, 15, 16])
+def test_small_vs_definition(T, api, orc, N, mode, acc):
+    A, g = I.random_symmetric(N, 5000 + N)
+    A = A.copy()
+    np.fill_diagonal(A, 7.5 + 2j)  # ignored by plain lhaf
+    want = orc.lhaf_memo(A, g, prec="f128")
+    got = api.lhaf(dev(T, A), dev(T, g), sum=mode, acc=acc).item()
+    print(f"N={N} mode={mode} acc={acc} got={got} want={want}", flush=True)
+    assert rel(got, want) < 1e-11
+
+
+def test_empty(T, api):
+    A = T.zeros((0, 0), dtype=T.complex128, device="cuda")
+    g = T.zeros(0, dtype=T.complex128, device="cuda")
+    assert api.lhaf(A, g).item() == 1
+
+
+def test_single16(T, api, orc):
+    A, g = I.single16()
+    want = orc.lhaf_memo(A, g, prec="f128")
+    for mode in ("fds", "et"):
+        got, err = api.lhaf(dev(T, A), dev(T, g), sum=mode, return_error=True)
+        print("single16", mode, got.item(), want, err.item(), flush=True)
+        assert rel(got.item(), want) < 1e-12
+        assert abs(got.item() - want) <= max(err.item(), 1e-30) * 10
+
+
+def et_tolerance(orc, A, g):
+    """ET cancels: the signed sum is kappa = sum|c_t f_t| / |sum c_t f_t| times
+    smaller than its terms, and each term carries a relative error of at most
+    ~1e-14 (Hessenberg + characteristic polynomial in double), so the bound is
+    kappa * 1e-14 (never below 1e-12)."""
+    v, ab = orc.lhaf_sum(A, g, mode="et", with_abs=True)
+    return max(1e-12, 1e-14 * ab / abs(v))
+
+
+@pytest.mark.parametrize("N", [20, 24])
+def test_medium_vs_oracle(T, api, orc, N):
+    A, g = I.gaussian_state_matrix(N, np.random.Generator(np.random.PCG64(77 + N)))
+    want = orc.lhaf_memo(A, g) if N <= 22 else orc.lhaf_sum(A, g, prec="f64")
+    got = api.lhaf(dev(T, A), dev(T, g), sum="fds").item()
+    print(N, "fds", got, want, flush=True)
+    assert rel(got, want) < 1e-12
+    got = api.lhaf(dev(T, A), dev(T, g), sum="et").item()
+    tol = et_tolerance(orc, A, g)
+    print(N, "et", got, want, tol, flush=True)
+    assert rel(got, want) < tol
+
+
+@pytest.mark.parametrize("r", [[2], [4], [3, 1], [2, 2], [2, 1, 0, 3], [3, 3, 1], [1, 1, 1, 1, 1],
+                               [5, 2], [4, 3, 2, 1], [2, 2, 2, 2, 1]])
+@pytest.mark.parametrize("mode", ["fds", "et"])
+def test_repeated_vs_explicit(T, api, orc, r, mode):
+    A, g = I.random_symmetric(len(r), 6000 + 13 * sum(r) + len(r))
+    want = orc.lhaf_repeated(A, g, r, method="explicit", prec="f128")
+    got = api.lhaf(dev(T, A), dev(T, g), r=r, sum=mode).item()
+    print(r, mode, got, want, flush=True)
+    assert rel(got, want) < 1e-11
+
+
+def test_repeated_all_ones_equals_plain(T, api):
+    A, g = I.random_symmetric(10, 4242)
+    a = api.lhaf(dev(T, A), dev(T, g)).item()
+    b = api.lhaf(dev(T, A), dev(T, g), r=[1] * 10).item()
+    assert rel(b, a) < 1e-13
+
+
+def test_term_range_matches_oracle(T, api, orc):
+    """Partial sums over term ranges follow the documented enumeration.  A
+    single term depends on the reduced matrix's diagonal, which plain lhaf
+    ignores (the library uses 0 there), so the matrix has a zero diagonal."""
+    A, g = I.random_symmetric(14, 99)
+    A = A.copy()
+    np.fill_diagonal(A, 0.0)
+    for (t0, t1) in [(0, 7), (7, 40), (40, 64), (13, 14)]:
+        want = orc.lhaf_sum(A, g, t0=t0, t1=t1, scaled=False)
+        got = api.lhaf(dev(T, A), dev(T, g), term_begin=t0, term_end=t1, scaled=False).item()
+        assert rel(got, want) < 1e-12, (t0, t1)
+
+
+def test_batched_dense_matches_single(T, api, orc):
+    rng = np.random.Generator(np.random.PCG64(31337))
+    mats = [I.gaussian_state_matrix(12, rng) for _ in range(5)]
+    A = np.stack([m[0] for m in mats])
+    g = np.stack([m[1] for m in mats])
+    got = api.lhaf_batched(dev(T, A), dev(T, g)).cpu().numpy()
+    for b in range(5):
+        want = orc.lhaf_memo(A[b], g[b], prec="f128")
+        assert rel(got[b], want) < 1e-12
+
+
+def test_batched_shared_base_uneven(T, api, orc):
+    base = I.state100(0)
+    B, gam = base["B"], base["gamma"]
+    rng = np.random.Generator(np.random.PCG64(7))
+    sizes = [2, 5, 8, 11, 16, 3]
+    idx = [np.sort(rng.permutation(100)[:s]) for s in sizes]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    got = api.lhaf_batched(dev(T, B), dev(T, gam), idx=np.concatenate(idx), idx_off=off).cpu().numpy()
+    for k, ix in enumerate(idx):
+        want = orc.lhaf_memo(B[np.ix_(ix, ix)], gam[ix], prec="f128")
+        assert rel(got[k], want) < 1e-11, k
