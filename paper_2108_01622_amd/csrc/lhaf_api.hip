@@ -17,6 +17,7 @@
 #include "lhaf_internal.h"
 // kernels (one translation unit with the launches)
 #include "lhaf_forward.hip"
+#include "lhaf_backward.hip"
 
 namespace lh {
 
@@ -555,14 +556,139 @@ lh_status lhaf_repeated(const lh_c128* A, int64_t lda, const lh_c128* gamma, con
                       o.ws_bytes, o, (hipStream_t)stream, false, nullptr);
 }
 
-size_t lhaf_backward_workspace(int32_t, const int64_t*, const int32_t*, int32_t, const lh_opts*) {
-  return 0;
+static lh_status backward_impl(int32_t B, const lh_c128* A_base, int64_t lda, int64_t stride_A,
+                               const lh_c128* gamma_base, int64_t stride_g, const int32_t* idx,
+                               const int64_t* idx_off, const int32_t* r, const lh_c128* grad_out,
+                               lh_c128* dA, lh_c128* dgamma, int32_t base_dim, void* workspace,
+                               size_t ws_bytes, const lh_opts& o, hipStream_t st, bool query_only,
+                               size_t* need_bytes) {
+  if (B < 0 || !idx_off) return LH_EINVAL;
+  std::vector<ProblemIn> pin(B);
+  for (int b = 0; b < B; ++b) {
+    const int64_t s0 = idx_off[b], s1 = idx_off[b + 1];
+    if (s1 < s0 || s0 < 0) return LH_EINVAL;
+    const int64_t N = s1 - s0;
+    if (r) {
+      int64_t tot = 0;
+      for (int64_t k = s0; k < s1; ++k) {
+        if (r[k] < 0) return LH_EINVAL;
+        tot += r[k];
+      }
+      if (N > kMaxN || tot > kMaxN) return LH_ESIZE;
+      pin[b].plan = plan_repeated(r + s0, (int)N);
+    } else {
+      if (N > kMaxN) return LH_ESIZE;
+      pin[b].plan = plan_plain((int)N);
+    }
+    pin[b].a_off = (int64_t)b * stride_A;
+    pin[b].g_off = (int64_t)b * stride_g;
+    pin[b].i_off = s0;
+  }
+  int dev = 0;
+  lh_status s = ensure_device(dev);
+  if (s != LH_OK) return s;
+  lh_opts ob = o;
+  ob.term_begin = 0;
+  ob.term_end = -1;
+  ob.scaled = 1;
+  Plan pl;
+  s = build_plan(pin, ob, dev, pl, true);
+  if (s != LH_OK) return s;
+  size_t gtot = 0;
+  for (auto& P : pl.probs) {
+    P.g_off = (int64_t)gtot;
+    gtot += (size_t)P.n_items * bwd_item_elems(P.B);
+  }
+  gtot = std::max<size_t>(gtot, 64);
+  const size_t scr = (size_t)pl.grid * bwd_wave_scratch_elems(pl.bmax);
+  const size_t off_g = pl.lay.total;
+  const size_t off_s = align_up(off_g + gtot * sizeof(cd));
+  const size_t total = align_up(off_s + scr * sizeof(cd));
+  if (query_only) {
+    *need_bytes = total;
+    return LH_OK;
+  }
+  if (B == 0) return LH_OK;
+  if (!A_base || !gamma_base || !grad_out || !dA || !dgamma || lda < 1) return LH_EINVAL;
+  if (stride_A == 0 && base_dim < 1) return LH_EINVAL;
+  if (!workspace) return LH_EINVAL;
+  if (ws_bytes < total) return LH_ENOMEM;
+  char* base = static_cast<char*>(workspace);
+  s = upload_plan(pl, base, st, dev);
+  if (s != LH_OK) return s;
+  const int nprob = (int)pl.probs.size();
+  hipLaunchKernelGGL(pack_kernel, dim3(nprob), dim3(256), 0, st,
+                     reinterpret_cast<const Prob*>(base + pl.lay.probs),
+                     reinterpret_cast<const int64_t*>(base + pl.lay.aoff),
+                     reinterpret_cast<const int64_t*>(base + pl.lay.goff),
+                     reinterpret_cast<const int64_t*>(base + pl.lay.ioff), A_base, lda, gamma_base,
+                     idx, reinterpret_cast<cd*>(base + pl.lay.cdata),
+                     reinterpret_cast<int*>(base + pl.lay.counter));
+  if (hipGetLastError() != hipSuccess) return LH_EHIP;
+  cd* gsl = reinterpret_cast<cd*>(base + off_g);
+  cd* scratch = reinterpret_cast<cd*>(base + off_s);
+  if (!pl.items.empty()) {
+    const size_t lds = lds_bytes_for(std::max(pl.nmax, 1));
+#define LH_BLAUNCH(BB)                                                                          \
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(backward_kernel<BB>), dim3(pl.grid), dim3(64), lds, st,    \
+                     reinterpret_cast<const Prob*>(base + pl.lay.probs),                        \
+                     reinterpret_cast<const Item*>(base + pl.lay.items), (int)pl.items.size(),  \
+                     reinterpret_cast<int*>(base + pl.lay.counter),                             \
+                     reinterpret_cast<const cd*>(base + pl.lay.cdata), gsl, scratch,            \
+                     std::max(pl.nmax, 1))
+    switch (pl.bmax) {
+      case 1: LH_BLAUNCH(1); break;
+      case 2: LH_BLAUNCH(2); break;
+      case 3: LH_BLAUNCH(3); break;
+      case 4: LH_BLAUNCH(4); break;
+      case 5: LH_BLAUNCH(5); break;
+      case 6: LH_BLAUNCH(6); break;
+      case 7: LH_BLAUNCH(7); break;
+      default: LH_BLAUNCH(8); break;
+    }
+#undef LH_BLAUNCH
+    if (hipGetLastError() != hipSuccess) return LH_EHIP;
+  }
+  hipLaunchKernelGGL(greduce_kernel, dim3(nprob), dim3(256), 0, st,
+                     reinterpret_cast<const Prob*>(base + pl.lay.probs), gsl);
+  if (hipGetLastError() != hipSuccess) return LH_EHIP;
+  if (stride_A != 0) {
+    hipLaunchKernelGGL(scatter_dense_kernel, dim3(nprob), dim3(256), 0, st,
+                       reinterpret_cast<const Prob*>(base + pl.lay.probs), gsl, grad_out, dA, lda,
+                       stride_A, dgamma, stride_g);
+  } else {
+    const int64_t E = (int64_t)base_dim * base_dim + base_dim;
+    hipLaunchKernelGGL(scatter_shared_kernel, dim3((unsigned)((E + 127) / 128)), dim3(128), 0, st,
+                       reinterpret_cast<const Prob*>(base + pl.lay.probs), nprob,
+                       reinterpret_cast<const int64_t*>(base + pl.lay.ioff), idx, gsl, grad_out,
+                       dA, lda, dgamma, base_dim);
+  }
+  if (hipGetLastError() != hipSuccess) return LH_EHIP;
+  return LH_OK;
 }
 
-lh_status lhaf_backward(int32_t, const lh_c128*, int64_t, int64_t, const lh_c128*, int64_t,
-                        const int32_t*, const int64_t*, const int32_t*, const lh_c128*, lh_c128*,
-                        lh_c128*, int32_t, void*, size_t, const lh_opts*, void*) {
-  return LH_EUNSUPPORTED;
+size_t lhaf_backward_workspace(int32_t B, const int64_t* idx_off, const int32_t* r,
+                               int32_t base_dim, const lh_opts* opts) {
+  lh_opts o;
+  if (validate_opts(opts, o) != LH_OK) return 0;
+  size_t need = 0;
+  if (backward_impl(B, nullptr, 1, 0, nullptr, 0, nullptr, idx_off, r, nullptr, nullptr, nullptr,
+                    base_dim, nullptr, 0, o, nullptr, true, &need) != LH_OK)
+    return 0;
+  return need;
+}
+
+lh_status lhaf_backward(int32_t B, const lh_c128* A_base, int64_t lda, int64_t stride_A,
+                        const lh_c128* gamma_base, int64_t stride_g, const int32_t* idx,
+                        const int64_t* idx_off, const int32_t* r, const lh_c128* grad_out,
+                        lh_c128* dA, lh_c128* dgamma, int32_t base_dim, void* workspace,
+                        size_t ws_bytes, const lh_opts* opts, void* stream) {
+  lh_opts o;
+  lh_status s = validate_opts(opts, o);
+  if (s != LH_OK) return s;
+  return backward_impl(B, A_base, lda, stride_A, gamma_base, stride_g, idx, idx_off, r, grad_out,
+                       dA, dgamma, base_dim, workspace, ws_bytes, o, (hipStream_t)stream, false,
+                       nullptr);
 }
 
 }  // extern "C"

@@ -1,0 +1,470 @@
+// Adjoint kernels: gradients of loop hafnians (the paper has none; this is
+// the reverse pass of the per-term power-trace recursion of App. B.1/B.2).
+//
+// Per term, with W = C X_d, u = X_d v, g_k = Tr(W^k)/(2k) + u^T W^{k-1} v / 2
+// and f = [lambda^n] exp(sum_k g_k lambda^k) = sum_j ... with coefficients
+// e_j = [lambda^j] exp(G):
+//   d f / d g_k = e_{n-k}                    (d exp(G)/d g_k = lambda^k exp(G))
+//   a_k := e_{n-k} / 2
+//   (d f / d W)^T = P(W) + sum_{i+j<=n-2} a_{i+j+2} b_j alpha_i^T
+//       P(x) = sum_{k=1..n} a_k x^{k-1},  b_j = W^j v,  alpha_i = (W^T)^i u
+//   d f / d v = sum_k a_k (alpha_{k-1} + X_d b_{k-1})
+//   d f / d C = (d f / d W) X_d.
+// P(W) is evaluated by Paterson-Stockmeyer (s = ceil(sqrt n): powers
+// W^1..W^s, then Horner in W^s), the dense contraction of this path; the
+// products keep one operand in registers (8 x 8 lane grid, row broadcasts by
+// ds_bpermute) and stream the other from a per-wavefront scratch in global
+// memory.  Terms are recomputed per subset; nothing is stored across terms
+// except the running gradient of the item.
+namespace lh {
+
+constexpr int kMaxPS = 6;  // ceil(sqrt(32))
+
+__host__ __device__ inline size_t bwd_wave_scratch_elems(int B) {
+  const size_t LD = 8 * (size_t)B;
+  return kMaxPS * LD * LD + 2 * 33 * 64;
+}
+__host__ __device__ inline size_t bwd_item_elems(int B) {
+  const size_t LD = 8 * (size_t)B;
+  return LD * LD + 64;
+}
+
+// R <- R * M with R in registers (lane (p,q) holds R[8a+p][8k+q]) and M
+// row-major LD x LD in global memory.
+template <int B>
+__device__ __forceinline__ void mul_right(double (&Rr)[B][B], double (&Ri)[B][B],
+                                          const cd* __restrict__ M, const int p, const int q) {
+  constexpr int LD = 8 * B;
+  double Or[B][B], Oi[B][B];
+#pragma unroll
+  for (int a = 0; a < B; ++a)
+#pragma unroll
+    for (int k = 0; k < B; ++k) Or[a][k] = Oi[a][k] = 0.0;
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+#pragma unroll 2
+    for (int r = 0; r < 8; ++r) {
+      const int l = 8 * b + r;
+      cd mrow[B];
+#pragma unroll
+      for (int k = 0; k < B; ++k) mrow[k] = M[l * LD + 8 * k + q];
+      const int src = (p << 3) | r;
+#pragma unroll
+      for (int a = 0; a < B; ++a) {
+        const cd x = mk(shfl_d(Rr[a][b], src), shfl_d(Ri[a][b], src));
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+          const cd o = cfma(x, mrow[k], mk(Or[a][k], Oi[a][k]));
+          Or[a][k] = o.r;
+          Oi[a][k] = o.i;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < B; ++a)
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      Rr[a][k] = Or[a][k];
+      Ri[a][k] = Oi[a][k];
+    }
+}
+
+template <int B>
+__device__ __forceinline__ void store_mat(const double (&Rr)[B][B], const double (&Ri)[B][B],
+                                          cd* __restrict__ M, const int p, const int q) {
+  constexpr int LD = 8 * B;
+#pragma unroll
+  for (int a = 0; a < B; ++a)
+#pragma unroll
+    for (int k = 0; k < B; ++k) M[(8 * a + p) * LD + 8 * k + q] = mk(Rr[a][k], Ri[a][k]);
+}
+
+// Krylov sequences b_j = W^j v and alpha_i = (W^T)^i u (u = X_d v) for
+// 0 <= i, j < n, stored in the wavefront scratch (row index = vertex), and
+// the loop moments mu_k = u . b_{k-1} into L.mu.
+template <int B>
+__device__ __forceinline__ void krylov_pair(const double (&Wr)[B][B], const double (&Wi)[B][B],
+                                            const double (&dcol)[B], const cd* __restrict__ vp,
+                                            const int m, const int H, const int n, const int p,
+                                            const int q, const int lane, cd* __restrict__ bv,
+                                            cd* __restrict__ av, LdsView& L) {
+  // b_0 = v, alpha_0 = u
+  bv[lane] = vp[lane];
+  // u_c = d_{pair(c)} v_{partner(c)}: column c = 8k+q held with dcol[k]
+  if (p == 0) {
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const int c = 8 * k + q;
+      const int pc = c < H ? c + H : c - H;
+      av[c] = c < m ? cscale(dcol[k], vp[pc & 63]) : czero();
+    }
+  }
+  __syncthreads();
+  for (int j = 0; j + 1 < n; ++j) {
+    // b_{j+1} = W b_j : row sums; lane needs b_j at its columns
+    cd xc[B], xr[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) xc[k] = bv[64 * j + 8 * k + q];
+#pragma unroll
+    for (int a = 0; a < B; ++a) xr[a] = av[64 * j + 8 * a + p];
+    cd y[B], z[B];
+#pragma unroll
+    for (int a = 0; a < B; ++a) {
+      y[a] = czero();
+#pragma unroll
+      for (int k = 0; k < B; ++k) y[a] = cfma(mk(Wr[a][k], Wi[a][k]), xc[k], y[a]);
+      y[a] = sum_row8(y[a]);
+    }
+    // alpha_{j+1} = W^T alpha_j : column sums; lane needs alpha_j at its rows
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      z[k] = czero();
+#pragma unroll
+      for (int a = 0; a < B; ++a) z[k] = cfma(mk(Wr[a][k], Wi[a][k]), xr[a], z[k]);
+      z[k] = sum_col8(z[k]);
+    }
+    if (q == 0) {
+#pragma unroll
+      for (int a = 0; a < B; ++a) bv[64 * (j + 1) + 8 * a + p] = y[a];
+    }
+    if (p == 0) {
+#pragma unroll
+      for (int k = 0; k < B; ++k) av[64 * (j + 1) + 8 * k + q] = z[k];
+    }
+    __syncthreads();
+  }
+  // mu_k = sum_c u_c b_{k-1}[c], lanes over c
+  for (int k = 1; k <= n; ++k) {
+    double re = 0.0, im = 0.0;
+    if (lane < m) {
+      const cd t = cmul(av[lane], bv[64 * (k - 1) + lane]);
+      re = t.r;
+      im = t.i;
+    }
+    // full-wave sum: row groups then column groups
+    re = sum_col8(sum_row8(re));
+    im = sum_col8(sum_row8(im));
+    if (lane == 0) L.mu[k] = mk(re, im);
+  }
+  __syncthreads();
+}
+
+// Gradient of the terms [t0, t1) of problem P into the item slot
+// G[LD*LD] (accumulated as sum_t c_t d_{pair(j)} M_t[j][c], M = (d f/d W)^T)
+// and G[LD*LD + l] (d f / d v_l).
+template <int B>
+__device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, const int64_t t1,
+                                             const cd* __restrict__ Cp,
+                                             const cd* __restrict__ vp, cd* __restrict__ G,
+                                             cd* __restrict__ scr, LdsView& L) {
+  constexpr int LD = 8 * B;
+  const int lane = threadIdx.x & 63;
+  const int p = lane >> 3, q = lane & 7;
+  const int m = P.m, H = P.H, n = P.n;
+  cd* pw = scr;                          // [kMaxPS][LD*LD] powers W^1..W^s
+  cd* bv = scr + kMaxPS * LD * LD;       // [33][64] b_j
+  cd* av = bv + 33 * 64;                 // [33][64] alpha_i
+  cd* acoef = L.wb;                      // a_1..a_n (index k)
+
+  // zero the item's accumulators
+#pragma unroll
+  for (int a = 0; a < B; ++a)
+#pragma unroll
+    for (int k = 0; k < B; ++k) G[(8 * a + p) * LD + 8 * k + q] = czero();
+  G[LD * LD + lane] = czero();
+
+  int s = 1;
+  while (s * s < n) ++s;
+  const int Q = (n + s - 1) / s - 1;
+
+  TermIter it = term_begin(P, t0, lane);
+  for (int64_t t = t0; t < t1; ++t) {
+    if (t != t0) term_next(it, H, lane);
+    double coef;
+    bool empty;
+    const double wl = term_weight(it, P, lane, coef, empty);
+    if (empty) {
+      __syncthreads();
+      continue;
+    }
+    double dcol[B], drow[B];
+    column_weights<B>(wl, m, H, q, dcol);
+#pragma unroll
+    for (int a = 0; a < B; ++a) {
+      const int i = 8 * a + p;
+      const int pi = i < H ? i : i - H;
+      const double d = shfl_d(wl, pi & 63);
+      drow[a] = i < m ? d : 0.0;
+    }
+    const int lpair = lane < H ? lane : lane - H;
+    const double dsh = shfl_d(wl, lpair & 63);
+    const double dlane = lane < m ? dsh : 0.0;
+
+    double Wr[B][B], Wi[B][B];
+    load_w<B>(Cp, dcol, p, q, Wr, Wi);
+    krylov_pair<B>(Wr, Wi, dcol, vp, m, H, n, p, q, lane, bv, av, L);
+    spectral_series<B>(Wr, Wi, m, n, p, q, lane, L);
+    // e_j = sum_k q_k L_{j-k};  a_k = e_{n-k} / 2 (k = 1..n)
+    if (lane >= 1 && lane <= n) {
+      const int j = n - lane;
+      cd e = czero();
+      for (int k = 0; k <= j; ++k) e = cfma(L.ser[k], L.ser[33 + j - k], e);
+      acoef[lane] = cscale(0.5, e);
+    }
+    __syncthreads();
+
+    // ---- P(W) = sum_{k=1..n} a_k W^{k-1} by Paterson-Stockmeyer
+    load_w<B>(Cp, dcol, p, q, Wr, Wi);
+    store_mat<B>(Wr, Wi, pw, p, q);  // W^1
+    __syncthreads();
+    for (int e = 2; e <= s; ++e) {
+      mul_right<B>(Wr, Wi, pw, p, q);  // W^e = W^{e-1} W
+      store_mat<B>(Wr, Wi, pw + (e - 1) * LD * LD, p, q);
+      __syncthreads();
+    }
+    // R = B_Q, then R <- R W^s + B_q for q = Q-1 .. 0, where
+    // B_q = sum_{r=0..s-1} a_{qs+r+1} W^r
+    double Rr[B][B], Ri[B][B];
+    for (int qq = Q; qq >= 0; --qq) {
+      if (qq != Q) mul_right<B>(Rr, Ri, pw + (s - 1) * LD * LD, p, q);
+#pragma unroll
+      for (int a = 0; a < B; ++a)
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+          cd acc = qq == Q ? czero() : mk(Rr[a][k], Ri[a][k]);
+          const int i = 8 * a + p, c = 8 * k + q;
+          for (int r = 0; r < s; ++r) {
+            const int kk = qq * s + r + 1;
+            if (kk > n) break;
+            const cd ak = acoef[kk];
+            if (r == 0) {
+              if (i == c && i < m) acc = cadd(acc, ak);
+            } else {
+              acc = cfma(ak, pw[(r - 1) * LD * LD + i * LD + c], acc);
+            }
+          }
+          Rr[a][k] = acc.r;
+          Ri[a][k] = acc.i;
+        }
+    }
+    // ---- + sum_i beta_i alpha_i^T, beta_i = sum_j a_{i+j+2} b_j
+    for (int i = 0; i + 2 <= n; ++i) {
+      cd beta[B], al[B];
+#pragma unroll
+      for (int a = 0; a < B; ++a) {
+        cd bsum = czero();
+        for (int j = 0; i + j + 2 <= n; ++j) bsum = cfma(acoef[i + j + 2], bv[64 * j + 8 * a + p], bsum);
+        beta[a] = bsum;
+      }
+#pragma unroll
+      for (int k = 0; k < B; ++k) al[k] = av[64 * i + 8 * k + q];
+#pragma unroll
+      for (int a = 0; a < B; ++a)
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+          const cd o = cfma(beta[a], al[k], mk(Rr[a][k], Ri[a][k]));
+          Rr[a][k] = o.r;
+          Ri[a][k] = o.i;
+        }
+    }
+    // ---- accumulate c_t d_{pair(row)} M[row][col]
+#pragma unroll
+    for (int a = 0; a < B; ++a) {
+      const double w = coef * drow[a];
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        cd* g = G + (8 * a + p) * LD + 8 * k + q;
+        *g = cfma(mk(w, 0.0), mk(Rr[a][k], Ri[a][k]), *g);
+      }
+    }
+    // ---- d f / d v_l = sum_k a_k (alpha_{k-1}[l] + d_{pair(l)} b_{k-1}[partner(l)])
+    if (lane < m) {
+      const int pl = lane < H ? lane + H : lane - H;
+      cd gsum = czero();
+      for (int k = 1; k <= n; ++k) {
+        const cd x = cfma(mk(dlane, 0.0), bv[64 * (k - 1) + pl], av[64 * (k - 1) + lane]);
+        gsum = cfma(acoef[k], x, gsum);
+      }
+      G[LD * LD + lane] = cfma(mk(coef, 0.0), gsum, G[LD * LD + lane]);
+    }
+    __syncthreads();
+  }
+}
+
+template <int BMAX>
+__global__ __launch_bounds__(64) void backward_kernel(const Prob* __restrict__ probs,
+                                                      const Item* __restrict__ items, int n_items,
+                                                      int* counter, const cd* __restrict__ ws,
+                                                      cd* __restrict__ gslots,
+                                                      cd* __restrict__ scratch, int nmax) {
+  extern __shared__ __align__(16) char lds_raw[];
+  LdsView L = carve(lds_raw, nmax);
+  const int lane = threadIdx.x & 63;
+  cd* scr = scratch + (size_t)blockIdx.x * bwd_wave_scratch_elems(BMAX);
+  for (;;) {
+    const int it = __builtin_amdgcn_readfirstlane(atomicAdd(counter, lane == 0 ? 1 : 0));
+    if (it >= n_items) break;
+    const Item I = items[it];
+    const Prob& P = probs[I.prob];
+    const int LD = 8 * P.B;
+    const cd* Cp = ws + P.c_off;
+    const cd* vp = Cp + LD * LD;
+    cd* G = gslots + P.g_off + (int64_t)(I.pad - P.first_item) * (LD * LD + 64);
+    switch (P.B) {
+#define LH_BCASE(BB)                                                                   \
+  case BB:                                                                             \
+    if (BB <= BMAX) run_item_bwd<(BB <= BMAX ? BB : 1)>(P, I.t0, I.t1, Cp, vp, G, scr, L); \
+    break;
+      LH_BCASE(1)
+      LH_BCASE(2)
+      LH_BCASE(3)
+      LH_BCASE(4)
+      LH_BCASE(5)
+      LH_BCASE(6)
+      LH_BCASE(7)
+      LH_BCASE(8)
+#undef LH_BCASE
+      default:
+        break;
+    }
+  }
+}
+
+// Sum the item gradients of each problem (in item order) into its first slot.
+__global__ void greduce_kernel(const Prob* __restrict__ probs, cd* __restrict__ gslots) {
+  const Prob& P = probs[blockIdx.x];
+  if (P.n_items <= 1) return;
+  const int LD = 8 * P.B;
+  const int E = LD * LD + 64;
+  cd* base = gslots + P.g_off;
+  for (int e = threadIdx.x; e < E; e += blockDim.x) {
+    cd acc = base[e];
+    for (int k = 1; k < P.n_items; ++k) acc = cadd(acc, base[(int64_t)k * E + e]);
+    base[e] = acc;
+  }
+}
+
+// d lhaf / d C[c][i] from the reduced accumulator (see run_item_bwd):
+// T[c][i] = scale * G[partner(i)][c].
+__device__ __forceinline__ cd grad_c(const Prob& P, const cd* __restrict__ G, int LD, int c, int i) {
+  const int pi = i < P.H ? i + P.H : i - P.H;
+  return cscale(P.scale, G[pi * LD + c]);
+}
+
+// Dense batch: problem b owns dA_b (N x N, lda) and dgamma_b; one block per
+// problem gathers every entry from the positions of its two vertices.
+__global__ void scatter_dense_kernel(const Prob* __restrict__ probs, const cd* __restrict__ gslots,
+                                     const lh_c128* __restrict__ grad_out, lh_c128* dA, int64_t lda,
+                                     int64_t strideA, lh_c128* dg, int64_t strideG) {
+  __shared__ int first[64], nxt[64];
+  const int b = blockIdx.x;
+  const Prob& P = probs[b];
+  const int N = P.Nvert;
+  if (threadIdx.x < 64) {
+    first[threadIdx.x] = -1;
+    nxt[threadIdx.x] = -1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int c = P.m - 1; c >= 0; --c) {
+      const int x = P.pos[c];
+      if (x >= 0) {
+        nxt[c] = first[x];
+        first[x] = c;
+      }
+    }
+  }
+  __syncthreads();
+  const int LD = 8 * P.B;
+  const cd* G = gslots + P.g_off;
+  const lh_c128 go = grad_out[b];
+  const cd gout = mk(go.re, go.im);
+  lh_c128* dAb = dA + (int64_t)b * strideA;
+  lh_c128* dgb = dg + (int64_t)b * strideG;
+  for (int e = threadIdx.x; e < N * N + N; e += blockDim.x) {
+    cd val = czero();
+    if (e < N * N) {
+      const int x = e / N, y = e % N;
+      for (int c = first[x]; c >= 0; c = nxt[c])
+        for (int i = first[y]; i >= 0; i = nxt[i]) {
+          if (c != i) {
+            val = cadd(val, cscale(0.5, cadd(grad_c(P, G, LD, c, i), grad_c(P, G, LD, i, c))));
+          } else {
+            const int pr = c < P.H ? c : c - P.H;
+            if ((P.diag_keep_mask >> pr) & 1) val = cadd(val, grad_c(P, G, LD, c, c));
+          }
+        }
+      const cd o = cmulj(gout, val);  // grad_out * conj(d lhaf / d A)
+      lh_c128 r;
+      r.re = o.r;
+      r.im = o.i;
+      dAb[(int64_t)x * lda + y] = r;
+    } else {
+      const int x = e - N * N;
+      for (int c = first[x]; c >= 0; c = nxt[c]) val = cadd(val, cscale(P.scale, G[LD * LD + c]));
+      const cd o = cmulj(gout, val);
+      lh_c128 r;
+      r.re = o.r;
+      r.im = o.i;
+      dgb[x] = r;
+    }
+  }
+}
+
+// Shared base matrix: entry (x, y) of dA (base_dim x base_dim) sums the
+// contributions of every problem, in problem order.
+__global__ void scatter_shared_kernel(const Prob* __restrict__ probs, int nprob,
+                                      const int64_t* __restrict__ ioff,
+                                      const int32_t* __restrict__ idx,
+                                      const cd* __restrict__ gslots,
+                                      const lh_c128* __restrict__ grad_out, lh_c128* dA,
+                                      int64_t lda, lh_c128* dg, int base_dim) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t E = (int64_t)base_dim * base_dim + base_dim;
+  if (e >= E) return;
+  cd tot = czero();
+  for (int b = 0; b < nprob; ++b) {
+    const Prob& P = probs[b];
+    if (P.n == 0) continue;
+    const int LD = 8 * P.B;
+    const cd* G = gslots + P.g_off;
+    const int32_t* ib = idx ? idx + ioff[b] : nullptr;
+    const lh_c128 go = grad_out[b];
+    cd val = czero();
+    if (e < (int64_t)base_dim * base_dim) {
+      const int x = (int)(e / base_dim), y = (int)(e % base_dim);
+      for (int c = 0; c < P.m; ++c) {
+        const int pc = P.pos[c];
+        if (pc < 0 || (ib ? ib[pc] : pc) != x) continue;
+        for (int i = 0; i < P.m; ++i) {
+          const int pi = P.pos[i];
+          if (pi < 0 || (ib ? ib[pi] : pi) != y) continue;
+          if (c != i) {
+            val = cadd(val, cscale(0.5, cadd(grad_c(P, G, LD, c, i), grad_c(P, G, LD, i, c))));
+          } else {
+            const int pr = c < P.H ? c : c - P.H;
+            if ((P.diag_keep_mask >> pr) & 1) val = cadd(val, grad_c(P, G, LD, c, c));
+          }
+        }
+      }
+    } else {
+      const int x = (int)(e - (int64_t)base_dim * base_dim);
+      for (int c = 0; c < P.m; ++c) {
+        const int pc = P.pos[c];
+        if (pc < 0 || (ib ? ib[pc] : pc) != x) continue;
+        val = cadd(val, cscale(P.scale, G[LD * LD + c]));
+      }
+    }
+    tot = cadd(tot, cmulj(mk(go.re, go.im), val));
+  }
+  lh_c128 r;
+  r.re = tot.r;
+  r.im = tot.i;
+  if (e < (int64_t)base_dim * base_dim)
+    dA[(e / base_dim) * lda + (e % base_dim)] = r;
+  else
+    dg[e - (int64_t)base_dim * base_dim] = r;
+}
+
+}  // namespace lh

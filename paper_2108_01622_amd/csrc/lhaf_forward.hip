@@ -243,7 +243,175 @@ struct HessLoop<B, B> {
 };
 
 // -------------------------------------------------------------------------
-// Evaluate terms [t0, t1) of problem P; returns the partial sum.
+// Term enumeration state: lane p (< H) holds the digit of pair p; pair 0 is
+// the fastest digit.
+struct TermIter {
+  int digit, eta_l, radix_l;
+};
+
+__device__ __forceinline__ TermIter term_begin(const Prob& P, const int64_t t0, const int lane) {
+  TermIter it;
+  it.eta_l = lane < P.H ? (int)P.eta[lane] : 0;
+  it.radix_l = lane < P.H ? (int)P.radix[lane] : 1;
+  it.digit = 0;
+  int64_t r = t0;
+  for (int pp = 0; pp < P.H; ++pp) {
+    const int R = P.radix[pp];
+    const int d = (int)(r % R);
+    r /= R;
+    if (lane == pp) it.digit = d;
+  }
+  return it;
+}
+
+__device__ __forceinline__ void term_next(TermIter& it, const int H, const int lane) {
+  const unsigned long long can = __ballot(lane < H && it.digit != it.radix_l - 1);
+  const int k = __ffsll((long long)can) - 1;
+  if (lane < k) it.digit = 0;
+  else if (lane == k) it.digit += 1;
+}
+
+// Weight of the lane's pair (d_p for FDS, z_p for ET) and the term's exact
+// integer coefficient c_t; `empty` marks the ET term with no pair (f = 0).
+__device__ __forceinline__ double term_weight(const TermIter& it, const Prob& P, const int lane,
+                                              double& coef, bool& empty) {
+  const bool fds = P.mode == 1;
+  double wl, fl;
+  if (fds) {
+    wl = (double)(it.eta_l - 2 * it.digit);
+    fl = ((it.digit & 1) ? -1.0 : 1.0) * c_binom[it.eta_l][it.digit];
+    if (lane == P.hp && 2 * it.digit != it.eta_l) fl *= 2.0;
+  } else {
+    wl = (double)it.digit;
+    fl = (((it.eta_l - it.digit) & 1) ? -1.0 : 1.0) * c_binom[it.eta_l][it.digit];
+  }
+  if (lane >= P.H) {
+    wl = 0.0;
+    fl = 1.0;
+  }
+  coef = prod_wave(fl);
+  empty = !fds && __ballot(lane < P.H && it.digit != 0) == 0ull;
+  return wl;
+}
+
+// d of the pairs of the lane's columns c = 8k+q (0 beyond m)
+template <int B>
+__device__ __forceinline__ void column_weights(const double wl, const int m, const int H,
+                                               const int q, double (&dcol)[B]) {
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    const int c = 8 * k + q;
+    const int pc = c < H ? c : c - H;
+    const double d = shfl_d(wl, pc & 63);
+    dcol[k] = c < m ? d : 0.0;
+  }
+}
+
+// W = C X_d: packed Cp holds C with partner-permuted columns
+template <int B>
+__device__ __forceinline__ void load_w(const cd* __restrict__ Cp, const double (&dcol)[B],
+                                       const int p, const int q, double (&Wr)[B][B],
+                                       double (&Wi)[B][B]) {
+  const int LD = 8 * B;
+#pragma unroll
+  for (int a = 0; a < B; ++a)
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const cd c = Cp[(8 * a + p) * LD + 8 * k + q];
+      Wr[a][k] = c.r * dcol[k];
+      Wi[a][k] = c.i * dcol[k];
+    }
+}
+
+// Loop moments mu_k = u^T W^{k-1} v (u = X_d v) into L.mu[1..n], from the
+// Krylov vectors x_i = W^i v: X_d W is symmetric, so
+//   mu_{2i+1} = x_i^T X_d x_i,  mu_{2i+2} = x_i^T X_d x_{i+1}.
+template <int B>
+__device__ __forceinline__ void loop_moments(const double (&Wr)[B][B], const double (&Wi)[B][B],
+                                             const double (&dcol)[B], const cd* __restrict__ vp,
+                                             const int m, const int H, const int n, const int p,
+                                             const int q, const int lane, LdsView& L) {
+  cd xc[B];
+#pragma unroll
+  for (int k = 0; k < B; ++k) xc[k] = vp[8 * k + q];
+  L.xb[lane] = vp[lane];
+  __syncthreads();
+  int cur = 0;
+  for (int i = 0; 2 * i + 1 <= n; ++i) {
+    const cd* xcur = L.xb + 64 * cur;
+    cd part = czero();
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const int c = 8 * k + q;
+      const int pc = c < H ? c + H : c - H;
+      if (c < m) part = cfma(cscale(dcol[k], xc[k]), xcur[pc & 63], part);
+    }
+    part = sum_row8(part);
+    if (lane == 0) L.mu[2 * i + 1] = part;
+    __syncthreads();
+    if (2 * i + 2 <= n) {
+      cd* xnext = L.xb + 64 * (cur ^ 1);
+      cd y[B];
+#pragma unroll
+      for (int a = 0; a < B; ++a) {
+        y[a] = czero();
+#pragma unroll
+        for (int k = 0; k < B; ++k) y[a] = cfma(mk(Wr[a][k], Wi[a][k]), xc[k], y[a]);
+        y[a] = sum_row8(y[a]);
+      }
+      if (q == 0) {
+#pragma unroll
+        for (int a = 0; a < B; ++a) xnext[8 * a + p] = y[a];
+      }
+      __syncthreads();
+      cd part2 = czero();
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int c = 8 * k + q;
+        const int pc = c < H ? c + H : c - H;
+        if (c < m) part2 = cfma(cscale(dcol[k], xc[k]), xnext[pc & 63], part2);
+      }
+      part2 = sum_row8(part2);
+      if (lane == 0) L.mu[2 * i + 2] = part2;
+#pragma unroll
+      for (int k = 0; k < B; ++k) xc[k] = xnext[8 * k + q];
+      cur ^= 1;
+      __syncthreads();
+    }
+  }
+}
+
+// Hessenberg reduction (destroys W) and characteristic polynomial of W, then
+// the two series of f(lambda) = c(lambda)^{-1/2} exp(M(lambda)),
+// M = sum_k mu_k lambda^k / 2:
+//   L.ser[0..n]      q_k, k q_k = -sum_{j=1..k} (k - j/2) c_j q_{k-j}
+//   L.ser[33..33+n]  L_k, k L_k = sum_{j=1..k} (j/2) mu_j L_{k-j}
+template <int B>
+__device__ __forceinline__ void spectral_series(double (&Wr)[B][B], double (&Wi)[B][B],
+                                                const int m, const int n, const int p,
+                                                const int q, const int lane, LdsView& L) {
+  if (lane <= n) L.ring[lane] = lane == 0 ? mk(1.0, 0.0) : czero();  // T_{-1} in slot 0
+  __syncthreads();
+  cd pi = czero(), hsub = czero();
+  HessLoop<B, 0>::run(Wr, Wi, m, n, p, q, lane, pi, hsub, L);
+  const cd* cpoly = L.ring + ring_slot(m - 1, L.NR) * L.NP;
+  if (lane < 2) {
+    const cd* xs = lane == 0 ? cpoly : L.mu;
+    cd* ys = L.ser + 33 * lane;
+    const double al = lane == 0 ? -1.0 : 0.0;
+    ys[0] = mk(1.0, 0.0);
+    for (int k = 1; k <= n; ++k) {
+      cd s = czero();
+      for (int jx = 1; jx <= k; ++jx)
+        s = cfma(cscale(fma(al, (double)k, 0.5 * jx), xs[jx]), ys[k - jx], s);
+      ys[k] = cscale(1.0 / k, s);
+    }
+  }
+  __syncthreads();
+}
+
+// -------------------------------------------------------------------------
+// Evaluate terms [t0, t1) of problem P; writes the item's partial sum.
 template <int B>
 __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const int64_t t1,
                                          const cd* __restrict__ Cp, const cd* __restrict__ vp,
@@ -251,149 +419,25 @@ __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const 
   const int lane = threadIdx.x & 63;
   const int p = lane >> 3, q = lane & 7;
   const int m = P.m, H = P.H, n = P.n;
-  const bool fds = P.mode == 1;
-  const int LD = 8 * B;
-  const int eta_l = lane < H ? (int)P.eta[lane] : 0;
-  const int radix_l = lane < H ? (int)P.radix[lane] : 1;
-  // digits of t0 (pair 0 fastest); lane p holds the digit of pair p
-  int digit = 0;
-  {
-    int64_t r = t0;
-    for (int pp = 0; pp < H; ++pp) {
-      const int R = P.radix[pp];
-      const int d = (int)(r % R);
-      r /= R;
-      if (lane == pp) digit = d;
-    }
-  }
-  // partner-column pair index of the lane's columns
-  int pcol[B];
-#pragma unroll
-  for (int k = 0; k < B; ++k) {
-    const int c = 8 * k + q;
-    pcol[k] = c < H ? c : c - H;
-  }
+  TermIter it = term_begin(P, t0, lane);
   dd accr = {0.0, 0.0}, acci = {0.0, 0.0};
   double sabs = 0.0;
 
   for (int64_t t = t0; t < t1; ++t) {
-    if (t != t0) {
-      const unsigned long long can = __ballot(lane < H && digit != radix_l - 1);
-      const int k = __ffsll((long long)can) - 1;
-      if (lane < k) digit = 0;
-      else if (lane == k) digit += 1;
-    }
-    double wl, fl;
-    if (fds) {
-      wl = (double)(eta_l - 2 * digit);
-      fl = ((digit & 1) ? -1.0 : 1.0) * c_binom[eta_l][digit];
-      if (lane == P.hp && 2 * digit != eta_l) fl *= 2.0;
-    } else {
-      wl = (double)digit;
-      fl = (((eta_l - digit) & 1) ? -1.0 : 1.0) * c_binom[eta_l][digit];
-    }
-    if (lane >= H) {
-      wl = 0.0;
-      fl = 1.0;
-    }
-    const double coef = prod_wave(fl);
-    const bool empty_set = !fds && __ballot(lane < H && digit != 0) == 0ull;  // ET z = 0: f = 0
-    if (empty_set) {
+    if (t != t0) term_next(it, H, lane);
+    double coef;
+    bool empty;
+    const double wl = term_weight(it, P, lane, coef, empty);
+    if (empty) {
       __syncthreads();
       continue;
     }
-
     double dcol[B];
-#pragma unroll
-    for (int k = 0; k < B; ++k) {
-      const int c = 8 * k + q;
-      double d = shfl_d(wl, pcol[k] & 63);
-      dcol[k] = c < m ? d : 0.0;
-    }
-    // W = C X_d : packed Cp holds C with partner-permuted columns
+    column_weights<B>(wl, m, H, q, dcol);
     double Wr[B][B], Wi[B][B];
-#pragma unroll
-    for (int a = 0; a < B; ++a)
-#pragma unroll
-      for (int k = 0; k < B; ++k) {
-        const cd c = Cp[(8 * a + p) * LD + 8 * k + q];
-        Wr[a][k] = c.r * dcol[k];
-        Wi[a][k] = c.i * dcol[k];
-      }
-
-    // ---- loop moments mu_k = u^T W^{k-1} v via x_i = W^i v:
-    //      mu_{2i+1} = x_i^T X_d x_i,  mu_{2i+2} = x_i^T X_d x_{i+1}
-    cd xc[B];
-#pragma unroll
-    for (int k = 0; k < B; ++k) xc[k] = vp[8 * k + q];
-    L.xb[lane] = vp[lane];
-    __syncthreads();
-    int cur = 0;
-    for (int i = 0; 2 * i + 1 <= n; ++i) {
-      const cd* xcur = L.xb + 64 * cur;
-      cd part = czero();
-#pragma unroll
-      for (int k = 0; k < B; ++k) {
-        const int c = 8 * k + q;
-        const int pc = c < H ? c + H : c - H;
-        if (c < m) part = cfma(cscale(dcol[k], xc[k]), xcur[pc & 63], part);
-      }
-      part = sum_row8(part);
-      if (lane == 0) L.mu[2 * i + 1] = part;
-      __syncthreads();
-      if (2 * i + 2 <= n) {
-        cd* xnext = L.xb + 64 * (cur ^ 1);
-        cd y[B];
-#pragma unroll
-        for (int a = 0; a < B; ++a) {
-          y[a] = czero();
-#pragma unroll
-          for (int k = 0; k < B; ++k) y[a] = cfma(mk(Wr[a][k], Wi[a][k]), xc[k], y[a]);
-          y[a] = sum_row8(y[a]);
-        }
-        if (q == 0) {
-#pragma unroll
-          for (int a = 0; a < B; ++a) xnext[8 * a + p] = y[a];
-        }
-        __syncthreads();
-        cd part2 = czero();
-#pragma unroll
-        for (int k = 0; k < B; ++k) {
-          const int c = 8 * k + q;
-          const int pc = c < H ? c + H : c - H;
-          if (c < m) part2 = cfma(cscale(dcol[k], xc[k]), xnext[pc & 63], part2);
-        }
-        part2 = sum_row8(part2);
-        if (lane == 0) L.mu[2 * i + 2] = part2;
-#pragma unroll
-        for (int k = 0; k < B; ++k) xc[k] = xnext[8 * k + q];
-        cur ^= 1;
-        __syncthreads();
-      }
-    }
-
-    // ---- Hessenberg reduction interleaved with the characteristic polynomial
-    if (lane <= n) L.ring[lane] = lane == 0 ? mk(1.0, 0.0) : czero();  // T_{-1} in slot 0
-    __syncthreads();
-    cd pi = czero(), hsub = czero();
-    HessLoop<B, 0>::run(Wr, Wi, m, n, p, q, lane, pi, hsub, L);
-
-    // ---- f = [lambda^n] c(lambda)^{-1/2} exp(M(lambda)), M = sum mu_k lambda^k / 2
-    //   lane 0: q_k with k q_k = -sum_{j=1..k} (k - j/2) c_j q_{k-j}
-    //   lane 1: L_k with k L_k = sum_{j=1..k} (j/2) mu_j L_{k-j}
-    const cd* cpoly = L.ring + ring_slot(m - 1, L.NR) * L.NP;
-    if (lane < 2) {
-      const cd* xs = lane == 0 ? cpoly : L.mu;
-      cd* ys = L.ser + 33 * lane;
-      const double al = lane == 0 ? -1.0 : 0.0;
-      ys[0] = mk(1.0, 0.0);
-      for (int k = 1; k <= n; ++k) {
-        cd s = czero();
-        for (int jx = 1; jx <= k; ++jx) s = cfma(cscale(fma(al, (double)k, 0.5 * jx), xs[jx]), ys[k - jx], s);
-        ys[k] = cscale(1.0 / k, s);
-      }
-    }
-    __syncthreads();
+    load_w<B>(Cp, dcol, p, q, Wr, Wi);
+    loop_moments<B>(Wr, Wi, dcol, vp, m, H, n, p, q, lane, L);
+    spectral_series<B>(Wr, Wi, m, n, p, q, lane, L);
     // every lane forms f and accumulates the same value (wave-uniform loop tail)
     cd f = czero();
     for (int k = 0; k <= n; ++k) f = cfma(L.ser[k], L.ser[33 + n - k], f);

@@ -24,7 +24,8 @@ struct Prob {
   int32_t mode;   // 0 ET, 1 FDS
   int32_t hp;     // FDS halving pair (-1 for ET)
   int32_t first_item, n_items;
-  int32_t base_dim_unused;
+  int32_t Nvert;  // vertices before padding (rows of the problem's matrix)
+  int64_t g_off;  // backward: offset (lh_c128 units) of the item gradient slots
   int32_t diag_keep_mask;  // bit p set: pair p repeats (eta >= 2), keep C's diagonal
   double scale;   // 2^-n for scaled FDS, 1 otherwise
   int8_t eta[kMaxPairs];

@@ -117,6 +117,7 @@ bool fill_prob(const PairPlan& pp, int mode, int64_t t0, int64_t t1, bool scaled
   pr->t1 = (t1 < 0 || t1 > pr->T) ? pr->T : t1;
   if (pr->t1 < pr->t0) pr->t1 = pr->t0;
   pr->m = 2 * pp.H;
+  pr->Nvert = pp.N;
   pr->H = pp.H;
   pr->n = pp.n;
   pr->B = (pr->m + 7) / 8;

@@ -1,0 +1,188 @@
+"""GPU parity of the adjoint (lhaf_backward) with the oracle's closed forms:
+  d lhaf / d gamma_i = lhaf(A without row/col i)
+  d lhaf / d A_ij    = lhaf(A without rows/cols i, j) / 2   (i != j; A read as sym(A))
+  repeated rows: r_i lhaf(A_{r-e_i}), r_i r_j lhaf(A_{r-e_i-e_j}) / 2,
+                 C(r_i, 2) lhaf(A_{r-2e_i}) on the diagonal
+and with identities that hold at any size (row expansion, Euler homogeneity,
+exact central differences: lhaf is affine in each symmetric entry).
+Returned values follow PyTorch's convention: grad_out * conj(derivative)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2108_01622_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2108_01622_amd import api as A
+    return A
+
+
+def rel(a, b):
+    return abs(complex(a) - complex(b)) / max(abs(complex(b)), 1e-300)
+
+
+def dev(T, x):
+    return T.as_tensor(np.ascontiguousarray(x), dtype=T.complex128, device="cuda")
+
+
+def grads(T, api, A, g, r=None, mode="fds"):
+    one = T.ones(1, dtype=T.complex128, device="cuda")
+    dA, dg = api.lhaf_backward(dev(T, A)[None], dev(T, g)[None], one, r=r, sum=mode)
+    return np.conj(dA[0].cpu().numpy()), np.conj(dg[0].cpu().numpy())
+
+
+@pytest.mark.parametrize("mode", ["fds", "et"])
+@pytest.mark.parametrize("N", [2, 3, 5, 8, 11])
+def test_closed_forms_small(T, api, orc, N, mode):
+    A, g = I.random_symmetric(N, 7000 + N)
+    A = A.copy()
+    np.fill_diagonal(A, 0.3 - 0.2j)
+    dA, dg = grads(T, api, A, g, mode=mode)
+    for i in range(N):
+        want = orc.lhaf_memo(*orc.remove(A, g, [i]), prec="f128")
+        assert rel(dg[i], want) < 1e-10, ("gamma", i)
+        assert abs(dA[i, i]) < 1e-13
+        for j in range(i + 1, N):
+            want = 0.5 * orc.lhaf_memo(*orc.remove(A, g, [i, j]), prec="f128")
+            assert rel(dA[i, j], want) < 1e-10, (i, j)
+            assert rel(dA[j, i], want) < 1e-10, (j, i)
+
+
+def test_gaussian_state_16(T, api, orc):
+    A, g = I.single16()
+    dA, dg = grads(T, api, A, g)
+    for i in (0, 7, 15):
+        assert rel(dg[i], orc.lhaf_memo(*orc.remove(A, g, [i]), prec="f128")) < 1e-10
+    for (i, j) in ((0, 1), (3, 12), (14, 15)):
+        assert rel(dA[i, j], 0.5 * orc.lhaf_memo(*orc.remove(A, g, [i, j]), prec="f128")) < 1e-10
+
+
+def reduce_r(r, *idx):
+    r = list(r)
+    for i in idx:
+        r[i] -= 1
+    return r
+
+
+@pytest.mark.parametrize("r", [[2, 1], [3, 2, 1], [2, 1, 0, 3], [4, 1], [2, 2, 1]])
+def test_repeated_closed_forms(T, api, orc, r):
+    M = len(r)
+    A, g = I.random_symmetric(M, 8000 + 17 * sum(r) + M)
+    dA, dg = grads(T, api, A, g, r=r)
+
+    def lr(rr):
+        if sum(rr) == 0:
+            return 1.0
+        return orc.lhaf_repeated(A, g, rr, method="explicit", prec="f128")
+
+    for i in range(M):
+        if r[i] == 0:
+            assert abs(dg[i]) < 1e-13 and np.all(np.abs(dA[i]) < 1e-13)
+            continue
+        assert rel(dg[i], r[i] * lr(reduce_r(r, i))) < 1e-10, ("gamma", i)
+        if r[i] >= 2:
+            assert rel(dA[i, i], math.comb(r[i], 2) * lr(reduce_r(r, i, i))) < 1e-10, ("diag", i)
+        for j in range(M):
+            if j != i and r[j] > 0:
+                want = 0.5 * r[i] * r[j] * lr(reduce_r(r, i, j))
+                assert rel(dA[i, j], want) < 1e-10, (i, j)
+
+
+def test_identities_n24(T, api, orc):
+    """Row expansion gamma_i dg_i + sum_j A_ij (2 dA_ij) = lhaf for every i;
+    Euler: sum_{i<j} A_ij (2 dA_ij) + sum_i gamma_i dg_i / 2 = (N/2) lhaf."""
+    A, g = I.gaussian_state_matrix(24, np.random.Generator(np.random.PCG64(2424)))
+    val = api.lhaf(dev(T, A), dev(T, g)).item()
+    dA, dg = grads(T, api, A, g)
+    N = 24
+    for i in range(N):
+        s = g[i] * dg[i] + sum(A[i, j] * 2 * dA[i, j] for j in range(N) if j != i)
+        assert rel(s, val) < 1e-10, i
+    e = sum(A[i, j] * 2 * dA[i, j] for i in range(N) for j in range(i + 1, N)) + 0.5 * np.dot(g, dg)
+    assert rel(e, N / 2 * val) < 1e-10
+
+
+def test_central_differences(T, api):
+    """lhaf is affine in each symmetric entry and in each gamma_i, so a central
+    difference has no truncation error; h = 1e-6 leaves roundoff ~ eps/h."""
+    A, g = I.gaussian_state_matrix(14, np.random.Generator(np.random.PCG64(1414)))
+    dA, dg = grads(T, api, A, g)
+    h = 1e-6
+    rng = np.random.Generator(np.random.PCG64(5))
+    for _ in range(6):
+        i, j = sorted(rng.choice(14, 2, replace=False))
+        Ap, Am = A.copy(), A.copy()
+        Ap[i, j] += h
+        Ap[j, i] += h
+        Am[i, j] -= h
+        Am[j, i] -= h
+        fd = (api.lhaf(dev(T, Ap), dev(T, g)).item() - api.lhaf(dev(T, Am), dev(T, g)).item()) / (2 * h)
+        assert rel(fd, 2 * dA[i, j]) < 1e-6, (i, j)
+    for i in (0, 9):
+        gp, gm = g.copy(), g.copy()
+        gp[i] += h
+        gm[i] -= h
+        fd = (api.lhaf(dev(T, A), dev(T, gp)).item() - api.lhaf(dev(T, A), dev(T, gm)).item()) / (2 * h)
+        assert rel(fd, dg[i]) < 1e-6
+
+
+def test_batched_dense_and_grad_out(T, api, orc):
+    rng = np.random.Generator(np.random.PCG64(99))
+    mats = [I.gaussian_state_matrix(n, rng) for n in (10, 10, 10)]
+    A = np.stack([m[0] for m in mats])
+    g = np.stack([m[1] for m in mats])
+    go = np.array([1.0, 0.5 - 2j, -1j])
+    dA, dg = api.lhaf_backward(dev(T, A), dev(T, g), dev(T, go))
+    dA, dg = dA.cpu().numpy(), dg.cpu().numpy()
+    for b in range(3):
+        want = orc.lhaf_memo(*orc.remove(A[b], g[b], [4]), prec="f128")
+        assert rel(dg[b, 4], go[b] * np.conj(want)) < 1e-10
+        want = 0.5 * orc.lhaf_memo(*orc.remove(A[b], g[b], [1, 8]), prec="f128")
+        assert rel(dA[b, 1, 8], go[b] * np.conj(want)) < 1e-10
+
+
+def test_shared_base_accumulates(T, api, orc):
+    base = I.state100(0)
+    Bm, gam = base["B"], base["gamma"]
+    idx = [np.array([3, 7, 10, 20, 51, 60]), np.array([7, 10, 33, 51]), np.array([3, 10, 99])]
+    off = np.array([0, 6, 10, 13], dtype=np.int64)
+    go = np.ones(3, dtype=complex)
+    dA, dg = api.lhaf_backward(dev(T, Bm), dev(T, gam), dev(T, go), idx=np.concatenate(idx), idx_off=off)
+    dA, dg = np.conj(dA.cpu().numpy()), np.conj(dg.cpu().numpy())
+    # gamma_10 appears in all three problems
+    want = 0.0
+    for ix in idx:
+        sub = list(ix)
+        k = sub.index(10)
+        As, gs = Bm[np.ix_(ix, ix)], gam[ix]
+        want += orc.lhaf_memo(*orc.remove(As, gs, [k]), prec="f128")
+    assert rel(dg[10], want) < 1e-10
+    # entry (7, 51) appears in problems 0 and 1
+    want = 0.0
+    for ix in idx[:2]:
+        sub = list(ix)
+        As, gs = Bm[np.ix_(ix, ix)], gam[ix]
+        want += 0.5 * orc.lhaf_memo(*orc.remove(As, gs, [sub.index(7), sub.index(51)]), prec="f128")
+    assert rel(dA[7, 51], want) < 1e-10
+    assert abs(dA[0, 1]) == 0 and abs(dg[1]) == 0
+
+
+def test_autograd_gradcheck(T, api):
+    A, g = I.random_symmetric(6, 606)
+    At = dev(T, A).requires_grad_(True)
+    gt = dev(T, g).requires_grad_(True)
+    assert T.autograd.gradcheck(lambda a, b: api.lhaf_autograd(a, b), (At, gt), eps=1e-6, atol=1e-7,
+                                rtol=1e-5, fast_mode=False)
