@@ -11,7 +11,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "liblhaf.so")
+LIB_PATH = os.environ.get("LHAF_LIBRARY") or os.path.join(_HERE, "_lib", "liblhaf.so")
 
 LH_SUM_ET, LH_SUM_FDS = 0, 1
 LH_ACC_FP64, LH_ACC_DD = 0, 1

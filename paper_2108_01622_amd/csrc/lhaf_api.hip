@@ -76,14 +76,16 @@ lh_status get_scratch(int dev, size_t bytes, void** out) {
 }
 
 // ---------------------------------------------------------------------------
-// schedules: persistent waves per CU x items per wave
+// schedules: items (term ranges) queued per resident wavefront.  The grid of
+// the persistent kernels is the number of wavefronts the chip keeps resident
+// (CUs x occupancy of the kernel instance), so a schedule only sets how
+// finely the term space is cut for load balance.
 struct Schedule {
-  int waves_per_cu;
   int items_per_wave;
 };
-const Schedule kSchedules[] = {{4, 4},  {8, 4},  {16, 4}, {4, 8},  {8, 8},
-                               {16, 8}, {8, 2},  {8, 16}, {16, 16}, {4, 16}};
+const Schedule kSchedules[] = {{1}, {2}, {4}, {8}, {16}, {32}};
 const int kNumSchedules = (int)(sizeof(kSchedules) / sizeof(kSchedules[0]));
+const int kDefaultSchedule = 2;
 
 // schedule cache: lines "bclass mode schedule" from $LHAF_TUNE_CACHE
 struct TuneCache {
@@ -109,7 +111,7 @@ int pick_schedule(const lh_opts* o, int bmax, int mode) {
     g_tune.loaded = true;
   }
   int s = g_tune.best[bmax][mode ? 1 : 0];
-  return s >= 0 ? s : 1;
+  return s >= 0 ? s : kDefaultSchedule;
 }
 
 // ---------------------------------------------------------------------------
@@ -157,6 +159,26 @@ struct Plan {
   Layout lay;
 };
 
+// wavefronts of one kernel instance resident per CU (occupancy query)
+int resident_per_cu(bool bwd, int bmax, int nmax) {
+  const size_t lds = lds_bytes_for(std::max(nmax, 1));
+  const void* fn = nullptr;
+  switch (bmax) {
+#define LH_FN(BB)                                                                      \
+  case BB:                                                                             \
+    fn = bwd ? reinterpret_cast<const void*>(&backward_kernel<BB>)                     \
+             : reinterpret_cast<const void*>(&forward_kernel<BB>);                     \
+    break;
+    LH_FN(1) LH_FN(2) LH_FN(3) LH_FN(4) LH_FN(5) LH_FN(6) LH_FN(7)
+    default: LH_FN(8)
+#undef LH_FN
+  }
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, 64, lds) != hipSuccess || blocks < 1)
+    blocks = 4;
+  return blocks;
+}
+
 // relative cost of one term with register tile B (Householder ~ m^3)
 double term_cost(int B) { return (double)B * B * B + 2.0; }
 
@@ -191,7 +213,7 @@ lh_status build_plan(std::vector<ProblemIn>& pin, const lh_opts& o, int dev, Pla
   const int sched = pick_schedule(&o, pl.bmax, mode_any);
   const Schedule S = kSchedules[sched];
   const int cus = g_dev[dev].cus;
-  const int waves = std::max(1, cus * S.waves_per_cu);
+  const int waves = std::max(1, cus * resident_per_cu(for_backward, pl.bmax, pl.nmax));
   const double target = std::max(total_cost / ((double)waves * S.items_per_wave), 1e-9);
   struct Tmp {
     int prob;

@@ -293,7 +293,10 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
 }
 
 template <int BMAX>
-__global__ __launch_bounds__(64) void backward_kernel(const Prob* __restrict__ probs,
+#ifndef LH_BWD_ATTR
+#define LH_BWD_ATTR __launch_bounds__(64)
+#endif
+__global__ LH_BWD_ATTR void backward_kernel(const Prob* __restrict__ probs,
                                                       const Item* __restrict__ items, int n_items,
                                                       int* counter, const cd* __restrict__ ws,
                                                       cd* __restrict__ gslots,

@@ -59,9 +59,12 @@ __device__ __forceinline__ int ring_slot(int k, int NR) { return (k + 1) % NR; }
 
 // -------------------------------------------------------------------------
 // One Householder step of the Hessenberg reduction: column j (= 8*kb + jj)
-// is reduced below the subdiagonal by W <- P W P, P = I - tau w w^*,
-// w = x + e^{i arg x_1} |x| e_1 (x = W[j+1:, j]).  With s = w^* W,
-// y = W w, alpha = w^* W w:  P W P = W - w (tau s) - (tau y - tau^2 alpha w) w^*.
+// is reduced below the subdiagonal by W <- P W P, P = I - tau w w^* (P is
+// Hermitian and unitary), w = x + e^{i arg x_1} |x| e_1 (x = W[j+1:, j]),
+// tau = 1 / (|x| (|x| + |x_1|)).  Applied as two rank-1 passes, left then
+// right, so only one reduction vector is live at a time:
+//   W <- W - w (tau s),  s = w^* W        (column sums over the lane grid)
+//   W <- W - (tau y) w^*, y = W w         (row sums over the lane grid)
 template <int B, int kb>
 __device__ __forceinline__ void householder_step(double (&Wr)[B][B], double (&Wi)[B][B],
                                                  const int jj, const int j, const int p,
@@ -101,60 +104,33 @@ __device__ __forceinline__ void householder_step(double (&Wr)[B][B], double (&Wi
   }
   __syncthreads();
   const double tau = L.sc[0];
-  const cd beta = mk(L.sc[1], L.sc[2]);
-  cd wr[B], wc[B];
+  // ---- left: W <- W - w (tau w^* W), rows >= 8kb, columns >= 8kb
+  {
+    cd wr[B];
 #pragma unroll
-  for (int a = 0; a < B; ++a) wr[a] = (a >= kb) ? L.wv[8 * a + p] : czero();
-#pragma unroll
-  for (int k = 0; k < B; ++k) wc[k] = (k >= kb) ? L.wv[8 * k + q] : czero();
-
-  // s_c = sum_i conj(w_i) W_ic (column sums), y_i = sum_c W_ic w_c (row sums)
-  cd s[B], y[B];
-#pragma unroll
-  for (int k = 0; k < B; ++k) {
-    s[k] = czero();
-    if (k < kb) continue;
-#pragma unroll
-    for (int a = 0; a < B; ++a) {
-      if (a < kb) continue;
-      s[k] = cjfma(wr[a], mk(Wr[a][k], Wi[a][k]), s[k]);
-    }
-    s[k] = sum_col8(s[k]);
-  }
-#pragma unroll
-  for (int a = 0; a < B; ++a) {
-    y[a] = czero();
+    for (int a = 0; a < B; ++a) wr[a] = (a >= kb) ? L.wv[8 * a + p] : czero();
 #pragma unroll
     for (int k = 0; k < B; ++k) {
       if (k < kb) continue;
-      y[a] = cfma(mk(Wr[a][k], Wi[a][k]), wc[k], y[a]);
-    }
-    y[a] = sum_row8(y[a]);
-  }
-  cd al = czero();
+      cd s = czero();
 #pragma unroll
-  for (int k = 0; k < B; ++k)
-    if (k >= kb) al = cfma(s[k], wc[k], al);
-  al = sum_row8(al);
-  const cd t2al = cscale(tau * tau, al);
+      for (int a = 0; a < B; ++a) {
+        if (a < kb) continue;
+        s = cjfma(wr[a], mk(Wr[a][k], Wi[a][k]), s);
+      }
+      s = cscale(tau, sum_col8(s));
 #pragma unroll
-  for (int a = 0; a < B; ++a) {
-    // z_a = tau y_a - tau^2 alpha w_a
-    cd z = cscale(tau, y[a]);
-    if (a >= kb) z = cfnma(t2al, wr[a], z);
-#pragma unroll
-    for (int k = 0; k < B; ++k) {
-      if (k < kb) continue;
-      cd w_ = mk(Wr[a][k], Wi[a][k]);
-      if (a >= kb) w_ = cfnma(wr[a], cscale(tau, s[k]), w_);
-      // w_ -= z * conj(wc_k)
-      cd zc = cmulj(z, wc[k]);
-      w_ = csub(w_, zc);
-      Wr[a][k] = w_.r;
-      Wi[a][k] = w_.i;
+      for (int a = 0; a < B; ++a) {
+        if (a < kb) continue;
+        const cd w_ = cfnma(wr[a], s, mk(Wr[a][k], Wi[a][k]));
+        Wr[a][k] = w_.r;
+        Wi[a][k] = w_.i;
+      }
     }
   }
+  // column j is now (.., beta, 0, ..) below row j; set it exactly
   if (q == jj) {
+    const cd beta = mk(L.sc[1], L.sc[2]);
 #pragma unroll
     for (int a = 0; a < B; ++a) {
       if (a < kb) continue;
@@ -165,6 +141,29 @@ __device__ __forceinline__ void householder_step(double (&Wr)[B][B], double (&Wi
       } else if (i > j + 1) {
         Wr[a][kb] = 0.0;
         Wi[a][kb] = 0.0;
+      }
+    }
+  }
+  // ---- right: W <- W - (tau W w) w^*, all rows, columns >= 8kb
+  {
+    cd wc[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) wc[k] = (k >= kb) ? L.wv[8 * k + q] : czero();
+#pragma unroll
+    for (int a = 0; a < B; ++a) {
+      cd y = czero();
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        if (k < kb) continue;
+        y = cfma(mk(Wr[a][k], Wi[a][k]), wc[k], y);
+      }
+      y = cscale(tau, sum_row8(y));
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        if (k < kb) continue;
+        const cd w_ = csub(mk(Wr[a][k], Wi[a][k]), cmulj(y, wc[k]));
+        Wr[a][k] = w_.r;
+        Wi[a][k] = w_.i;
       }
     }
   }
@@ -517,8 +516,14 @@ __global__ void pack_kernel(const Prob* __restrict__ probs, const int64_t* __res
   if (b == 0 && threadIdx.x == 0) *counter = 0;
 }
 
+// resident wavefronts per SIMD the register allocation aims for, by tile
+#ifndef LH_FWD_WAVES
+#define LH_FWD_WAVES(bmax) ((bmax) <= 2 ? 4 : ((bmax) <= 3 ? 3 : ((bmax) <= 5 ? 2 : 1)))
+#endif
+
 template <int BMAX>
-__global__ __launch_bounds__(64) void forward_kernel(const Prob* __restrict__ probs,
+__global__ __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(LH_FWD_WAVES(BMAX), LH_FWD_WAVES(BMAX)))) void forward_kernel(const Prob* __restrict__ probs,
                                                      const Item* __restrict__ items, int n_items,
                                                      int* counter, const cd* __restrict__ ws,
                                                      Partial* __restrict__ parts, int acc_dd,
