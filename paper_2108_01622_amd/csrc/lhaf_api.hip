@@ -432,7 +432,7 @@ int32_t lhaf_plan_pairs(int32_t N, const int32_t* r, int32_t* pos, int32_t* eta)
       if (r[i] < 0) return -LH_EINVAL;
       tot += r[i];
     }
-    if (tot > kMaxN) return -LH_ESIZE;
+    if (tot > kMaxN || N > kMaxRows) return -LH_ESIZE;
     pp = plan_repeated(r, N);
   } else {
     if (N > kMaxN) return -LH_ESIZE;
@@ -469,7 +469,7 @@ static lh_status batched_impl(int32_t B, const lh_c128* A_base, int64_t lda, int
         if (r[k] < 0) return LH_EINVAL;
         tot += r[k];
       }
-      if (N > kMaxN || tot > kMaxN) return LH_ESIZE;
+      if (N > kMaxRows || tot > kMaxN) return LH_ESIZE;
       pin[b].plan = plan_repeated(r + s0, (int)N);
     } else {
       if (N > kMaxN) return LH_ESIZE;
@@ -596,7 +596,7 @@ static lh_status backward_impl(int32_t B, const lh_c128* A_base, int64_t lda, in
         if (r[k] < 0) return LH_EINVAL;
         tot += r[k];
       }
-      if (N > kMaxN || tot > kMaxN) return LH_ESIZE;
+      if (N > kMaxRows || tot > kMaxN) return LH_ESIZE;
       pin[b].plan = plan_repeated(r + s0, (int)N);
     } else {
       if (N > kMaxN) return LH_ESIZE;

@@ -360,14 +360,13 @@ __device__ __forceinline__ cd grad_c(const Prob& P, const cd* __restrict__ G, in
 __global__ void scatter_dense_kernel(const Prob* __restrict__ probs, const cd* __restrict__ gslots,
                                      const lh_c128* __restrict__ grad_out, lh_c128* dA, int64_t lda,
                                      int64_t strideA, lh_c128* dg, int64_t strideG) {
-  __shared__ int first[64], nxt[64];
+  __shared__ short first[kMaxRows];
+  __shared__ short nxt[64];
   const int b = blockIdx.x;
   const Prob& P = probs[b];
   const int N = P.Nvert;
-  if (threadIdx.x < 64) {
-    first[threadIdx.x] = -1;
-    nxt[threadIdx.x] = -1;
-  }
+  for (int x = threadIdx.x; x < N; x += blockDim.x) first[x] = -1;
+  if (threadIdx.x < 64) nxt[threadIdx.x] = -1;
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int c = P.m - 1; c >= 0; --c) {

@@ -10,6 +10,7 @@ namespace lh {
 constexpr int kMaxN = 64;      // vertices per problem (after odd padding)
 constexpr int kMaxPairs = 32;  // distinct pairs H
 constexpr int kMaxB = 8;       // register tile: m <= 8*B, lane grid 8 x 8
+constexpr int kMaxRows = 4096; // rows of one repeated problem's matrix (modes)
 
 // One loop-hafnian problem as the kernels see it.
 struct Prob {
@@ -24,13 +25,13 @@ struct Prob {
   int32_t mode;   // 0 ET, 1 FDS
   int32_t hp;     // FDS halving pair (-1 for ET)
   int32_t first_item, n_items;
-  int32_t Nvert;  // vertices before padding (rows of the problem's matrix)
+  int32_t Nvert;  // rows of the problem's matrix (entries of its index list)
   int64_t g_off;  // backward: offset (lh_c128 units) of the item gradient slots
   int32_t diag_keep_mask;  // bit p set: pair p repeats (eta >= 2), keep C's diagonal
   double scale;   // 2^-n for scaled FDS, 1 otherwise
   int8_t eta[kMaxPairs];
   int8_t radix[kMaxPairs];
-  int8_t pos[kMaxN];  // entry index into the problem's index list, -1 = padding vertex
+  int16_t pos[kMaxN];  // entry index into the problem's index list, -1 = padding vertex
 };
 
 struct Item {
@@ -54,7 +55,8 @@ inline size_t lds_bytes_for(int nmax) {
 struct PairPlan {
   int H = 0;
   int n = 0;
-  int N = 0;  // vertices before padding
+  int N = 0;     // vertices before padding (photons for a repeated problem)
+  int rows = 0;  // rows of the problem's matrix
   bool padded = false;
   std::vector<int> pos;  // 2H
   std::vector<int> eta;  // H

@@ -14,6 +14,7 @@ namespace lh {
 PairPlan plan_plain(int N) {
   PairPlan pp;
   pp.N = N;
+  pp.rows = N;
   int Np = N + (N & 1);
   pp.padded = (N & 1) != 0;
   pp.n = Np / 2;
@@ -46,6 +47,7 @@ PairPlan plan_repeated(const int32_t* r, int M) {
       total += r[i];
     }
   pp.N = total;
+  pp.rows = M;
   std::vector<int> u, w;
   while (total > 1) {
     std::stable_sort(live.begin(), live.end(), [](const Cnt& a, const Cnt& b) {
@@ -117,7 +119,7 @@ bool fill_prob(const PairPlan& pp, int mode, int64_t t0, int64_t t1, bool scaled
   pr->t1 = (t1 < 0 || t1 > pr->T) ? pr->T : t1;
   if (pr->t1 < pr->t0) pr->t1 = pr->t0;
   pr->m = 2 * pp.H;
-  pr->Nvert = pp.N;
+  pr->Nvert = pp.rows;
   pr->H = pp.H;
   pr->n = pp.n;
   pr->B = (pr->m + 7) / 8;
@@ -130,7 +132,7 @@ bool fill_prob(const PairPlan& pp, int mode, int64_t t0, int64_t t1, bool scaled
     pr->radix[p] = (int8_t)((p == pr->hp) ? pp.eta[p] / 2 + 1 : pp.eta[p] + 1);
     if (pp.eta[p] >= 2) pr->diag_keep_mask |= 1 << p;
   }
-  for (int i = 0; i < kMaxN; ++i) pr->pos[i] = (i < 2 * pp.H) ? (int8_t)pp.pos[i] : (int8_t)-1;
+  for (int i = 0; i < kMaxN; ++i) pr->pos[i] = (i < 2 * pp.H) ? (int16_t)pp.pos[i] : (int16_t)-1;
   return true;
 }
 

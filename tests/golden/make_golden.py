@@ -55,12 +55,26 @@ def jobs():
                     eta=[p[2] for p in pairs] + ([1] if left is not None else []),
                     sha256=I.sha256_of(st["B"], st["gamma"], st["r"]))
     J["state100"] = rep
+    def rep128(st=st):
+        v = O.lhaf_repeated(st["B"], st["gamma"], st["r"], method="sum", mode="fds", prec="f128")
+        return dict(method="fds_f128 repeated pairs (greedy matching)", value=cx(v))
+    J["state100/f128"] = rep128
     A40, g40 = I.grad40()
     for b in GRAD40_SAMPLE:
         def g40job(b=b):
             v, ab = O.lhaf_sum(A40[b], g40[b], mode="fds", prec="f64", with_abs=True)
             return dict(method="fds_f64", value=cx(v), abs_sum=ab, sha256=I.sha256_of(A40[b], g40[b]))
         J[f"grad40/{b}"] = g40job
+    # closed-form derivatives of grad40[0]: d/d gamma_3 = lhaf(A_-3),
+    # d/d A_12 (entry of the full matrix read through sym(A)) = lhaf(A_-1,-2) / 2
+    def d_gamma(b=0, i=3):
+        Ar, gr = O.remove(A40[b], g40[b], [i])
+        return dict(method="fds_f64 of the minor", value=cx(O.lhaf_sum(Ar, gr, mode="fds", prec="f64")))
+    def d_a(b=0, i=1, j=2):
+        Ar, gr = O.remove(A40[b], g40[b], [i, j])
+        return dict(method="fds_f64 of the minor, halved", value=cx(0.5 * O.lhaf_sum(Ar, gr, mode="fds", prec="f64")))
+    J["grad40/0/dgamma3"] = d_gamma
+    J["grad40/0/dA1_2"] = d_a
     ch = I.chain4096()
     sizes = ch["sizes"]
     for N in range(20, 41, 2):
@@ -73,6 +87,11 @@ def jobs():
                 v, ab = O.lhaf_sum(A, g, mode="fds", prec="f64", with_abs=True)
                 return dict(method="fds_f64", value=cx(v), abs_sum=ab, N=int(len(ix)))
             J[f"chain4096/{b}"] = chjob
+    def ch128(b=0):
+        ix = ch["idx"][ch["idx_off"][b]:ch["idx_off"][b + 1]]
+        v = O.lhaf_sum(ch["B"][np.ix_(ix, ix)], ch["gamma"][ix], mode="fds", prec="f128")
+        return dict(method="fds_f128", value=cx(v), N=int(len(ix)))
+    J["chain4096/0/f128"] = ch128
     for n, cnt in ((52, DENSE52_BLOCK), (60, DENSE60_BLOCK)):
         for k in range(cnt):
             def bjob(n=n, k=k):
@@ -103,6 +122,8 @@ def main():
         res = fn()
         res["seconds"] = round(time.time() - t, 2)
         res["threads"] = a.threads
+        # merge with what other runs wrote meanwhile
+        data = json.load(open(OUT)) if os.path.exists(OUT) else data
         data[key] = res
         json.dump(data, open(OUT + ".tmp", "w"), indent=1, sort_keys=True)
         os.replace(OUT + ".tmp", OUT)
