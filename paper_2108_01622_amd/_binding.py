@@ -39,6 +39,7 @@ class LhafError(RuntimeError):
 
 
 _lib = None
+TUNE_CACHE = os.path.join(_HERE, "tune", "mi355x.txt")
 
 
 def lib():
@@ -47,6 +48,8 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise LhafError(f"HIP library not built: {LIB_PATH} (run paper_2108_01622_amd.build)")
+        if "LHAF_TUNE_CACHE" not in os.environ and os.path.exists(TUNE_CACHE):
+            os.environ["LHAF_TUNE_CACHE"] = TUNE_CACHE  # read lazily by the library
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
         P = ctypes.POINTER

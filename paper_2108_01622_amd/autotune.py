@@ -1,0 +1,94 @@
+"""Schedule autotuner for the persistent loop-hafnian launches.
+
+The library cuts each problem's term space into items (term ranges) taken
+from an atomic queue by the resident wavefronts; a schedule fixes how many
+items are queued per resident wavefront (``lhaf_schedule_count()`` choices).
+Few large items cost less queue traffic and per-item setup; many small items
+balance uneven batches.  This tool times every schedule on synthetic
+Gaussian-state problems of each register tile (B = ceil(N/8)) and sum mode,
+and writes the fastest as lines ``B mode schedule`` to a cache file that the
+library reads through $LHAF_TUNE_CACHE (the binding points it at the shipped
+file when the variable is unset).
+
+    python -m paper_2108_01622_amd.autotune [--out FILE] [--sizes 16 24 ...]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_CACHE = os.path.join(HERE, "tune", "mi355x.txt")
+
+
+def _problems(N: int, rng):
+    from . import inputs
+    # enough terms to time, bounded: about 2^21 terms per measurement
+    cap = 1 << 21
+    terms_each = 2 ** max(N // 2 - 1, 0)
+    count = int(max(1, min(256, cap // max(terms_each, 1))))
+    mats = [inputs.gaussian_state_matrix(N, rng) for _ in range(count)]
+    A = np.stack([m[0] for m in mats])
+    g = np.stack([m[1] for m in mats])
+    term_end = -1 if terms_each <= cap else cap
+    return A, g, term_end
+
+
+def tune(sizes=(16, 24, 32, 40, 48, 56, 64), modes=("fds", "et"), reps=2, verbose=True):
+    import torch
+    from . import api, _binding
+    nsched = int(_binding.lib().lhaf_schedule_count())
+    rng = np.random.Generator(np.random.PCG64(1622))
+    best, report = {}, []
+    for N in sizes:
+        B = math.ceil(N / 8)
+        A_np, g_np, term_end = _problems(N, rng)
+        A = torch.as_tensor(A_np, device="cuda")
+        g = torch.as_tensor(g_np, device="cuda")
+        for mode in modes:
+            times = []
+            for s in range(nsched):
+                kw = dict(sum=mode, schedule=s, scaled=term_end < 0, term_end=term_end)
+                api.lhaf_batched(A, g, **kw)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(reps):
+                    api.lhaf_batched(A, g, **kw)
+                torch.cuda.synchronize()
+                times.append((time.perf_counter() - t) / reps)
+            k = int(np.argmin(times))
+            best[(B, mode)] = k
+            row = dict(N=N, B=B, mode=mode, batch=len(A_np), best=k,
+                       times_ms=[round(1e3 * x, 3) for x in times])
+            report.append(row)
+            if verbose:
+                print(json.dumps(row), flush=True)
+    return best, report
+
+
+def write_cache(best, path=DEFAULT_CACHE):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        f.write("# B mode schedule (mode 0 = ET, 1 = FDS), written by paper_2108_01622_amd.autotune\n")
+        for (B, mode), s in sorted(best.items()):
+            f.write(f"{B} {1 if mode == 'fds' else 0} {s}\n")
+    return path
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_CACHE)
+    ap.add_argument("--sizes", type=int, nargs="*", default=[16, 24, 32, 40, 48, 56, 64])
+    ap.add_argument("--modes", nargs="*", default=["fds", "et"])
+    a = ap.parse_args()
+    best, _ = tune(a.sizes, a.modes)
+    print("wrote", write_cache(best, a.out))
+
+
+if __name__ == "__main__":
+    main()

@@ -101,10 +101,14 @@ int pick_schedule(const lh_opts* o, int bmax, int mode) {
     const char* path = std::getenv("LHAF_TUNE_CACHE");
     if (path) {
       if (FILE* f = std::fopen(path, "r")) {
-        int b, md, s;
-        while (std::fscanf(f, "%d %d %d", &b, &md, &s) == 3)
-          if (b >= 1 && b <= 8 && (md == 0 || md == 1) && s >= 0 && s < kNumSchedules)
+        char line[256];
+        while (std::fgets(line, sizeof(line), f)) {
+          int b, md, s;
+          if (line[0] == '#') continue;
+          if (std::sscanf(line, "%d %d %d", &b, &md, &s) == 3 && b >= 1 && b <= 8 &&
+              (md == 0 || md == 1) && s >= 0 && s < kNumSchedules)
             g_tune.best[b][md] = s;
+        }
         std::fclose(f);
       }
     }

@@ -20,9 +20,17 @@ namespace lh {
 
 constexpr int kMaxPS = 6;  // ceil(sqrt(32))
 
+// The same address as p, opaque to the optimiser (forces a fresh load).
+template <class T>
+__device__ __forceinline__ const T* launder_ptr(const T* p) {
+  uint64_t v = reinterpret_cast<uint64_t>(p);
+  asm volatile("" : "+s"(v));
+  return reinterpret_cast<const T*>(v);
+}
+
 __host__ __device__ inline size_t bwd_wave_scratch_elems(int B) {
   const size_t LD = 8 * (size_t)B;
-  return kMaxPS * LD * LD + 2 * 33 * 64;
+  return kMaxPS * LD * LD + 33 * 64;
 }
 __host__ __device__ inline size_t bwd_item_elems(int B) {
   const size_t LD = 8 * (size_t)B;
@@ -30,44 +38,59 @@ __host__ __device__ inline size_t bwd_item_elems(int B) {
 }
 
 // R <- R * M with R in registers (lane (p,q) holds R[8a+p][8k+q]) and M
-// row-major LD x LD in global memory.
-template <int B>
-__device__ __forceinline__ void mul_right(double (&Rr)[B][B], double (&Ri)[B][B],
-                                          const cd* __restrict__ M, const int p, const int q) {
-  constexpr int LD = 8 * B;
-  double Or[B][B], Oi[B][B];
+// row-major LD x LD in global memory (L2 resident).  Output row i needs only
+// input row i, so rows are done in groups of G local rows, in place: only the
+// group's accumulators are live, and M is streamed once per group.
+template <int B, int G, int A0>
+__device__ __forceinline__ void mul_rows(double (&Rr)[B][B], double (&Ri)[B][B],
+                                         const cd* __restrict__ M, const int p, const int q) {
+  if constexpr (A0 < B) {
+    constexpr int LD = 8 * B;
+    constexpr int NG = (A0 + G <= B) ? G : (B - A0);
+    double Or[NG][B], Oi[NG][B];
 #pragma unroll
-  for (int a = 0; a < B; ++a)
+    for (int a = 0; a < NG; ++a)
 #pragma unroll
-    for (int k = 0; k < B; ++k) Or[a][k] = Oi[a][k] = 0.0;
+      for (int k = 0; k < B; ++k) Or[a][k] = Oi[a][k] = 0.0;
 #pragma unroll
-  for (int b = 0; b < B; ++b) {
+    for (int b = 0; b < B; ++b) {
 #pragma unroll 2
-    for (int r = 0; r < 8; ++r) {
-      const int l = 8 * b + r;
-      cd mrow[B];
+      for (int r = 0; r < 8; ++r) {
+        const int l = 8 * b + r;
+        cd mrow[B];
 #pragma unroll
-      for (int k = 0; k < B; ++k) mrow[k] = M[l * LD + 8 * k + q];
-      const int src = (p << 3) | r;
+        for (int k = 0; k < B; ++k) mrow[k] = M[l * LD + 8 * k + q];
+        const int src = (p << 3) | r;
 #pragma unroll
-      for (int a = 0; a < B; ++a) {
-        const cd x = mk(shfl_d(Rr[a][b], src), shfl_d(Ri[a][b], src));
+        for (int a = 0; a < NG; ++a) {
+          const cd x = mk(shfl_d(Rr[A0 + a][b], src), shfl_d(Ri[A0 + a][b], src));
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-          const cd o = cfma(x, mrow[k], mk(Or[a][k], Oi[a][k]));
-          Or[a][k] = o.r;
-          Oi[a][k] = o.i;
+          for (int k = 0; k < B; ++k) {
+            const cd o = cfma(x, mrow[k], mk(Or[a][k], Oi[a][k]));
+            Or[a][k] = o.r;
+            Oi[a][k] = o.i;
+          }
         }
       }
     }
+#pragma unroll
+    for (int a = 0; a < NG; ++a)
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        Rr[A0 + a][k] = Or[a][k];
+        Ri[A0 + a][k] = Oi[a][k];
+      }
+    mul_rows<B, G, A0 + G>(Rr, Ri, M, p, q);
   }
-#pragma unroll
-  for (int a = 0; a < B; ++a)
-#pragma unroll
-    for (int k = 0; k < B; ++k) {
-      Rr[a][k] = Or[a][k];
-      Ri[a][k] = Oi[a][k];
-    }
+}
+
+// row-group size per tile: bounded accumulator footprint
+__host__ __device__ constexpr int mul_group(int B) { return B; }
+
+template <int B>
+__device__ __forceinline__ void mul_right(double (&Rr)[B][B], double (&Ri)[B][B],
+                                          const cd* __restrict__ M, const int p, const int q) {
+  mul_rows<B, mul_group(B), 0>(Rr, Ri, M, p, q);
 }
 
 template <int B>
@@ -80,71 +103,40 @@ __device__ __forceinline__ void store_mat(const double (&Rr)[B][B], const double
     for (int k = 0; k < B; ++k) M[(8 * a + p) * LD + 8 * k + q] = mk(Rr[a][k], Ri[a][k]);
 }
 
-// Krylov sequences b_j = W^j v and alpha_i = (W^T)^i u (u = X_d v) for
-// 0 <= i, j < n, stored in the wavefront scratch (row index = vertex), and
-// the loop moments mu_k = u . b_{k-1} into L.mu.
+// Krylov sequence b_j = W^j v (0 <= j < n) in the wavefront scratch (row
+// index = vertex) and the loop moments mu_k = u . b_{k-1} (u = X_d v) into
+// L.mu.  The second sequence alpha_i = (W^T)^i u needs no products: X_d W is
+// symmetric, so (W^T)^i X_d = X_d W^i and alpha_i = X_d b_i, i.e.
+// alpha_i[c] = d_{pair(c)} b_i[partner(c)].
 template <int B>
-__device__ __forceinline__ void krylov_pair(const double (&Wr)[B][B], const double (&Wi)[B][B],
-                                            const double (&dcol)[B], const cd* __restrict__ vp,
-                                            const int m, const int H, const int n, const int p,
-                                            const int q, const int lane, cd* __restrict__ bv,
-                                            cd* __restrict__ av, LdsView& L) {
-  // b_0 = v, alpha_0 = u
+__device__ __forceinline__ void krylov_b(const double (&Wr)[B][B], const double (&Wi)[B][B],
+                                         const double dlane, const cd* __restrict__ vp,
+                                         const int m, const int H, const int n, const int p,
+                                         const int q, const int lane, cd* __restrict__ bv,
+                                         LdsView& L) {
   bv[lane] = vp[lane];
-  // u_c = d_{pair(c)} v_{partner(c)}: column c = 8k+q held with dcol[k]
-  if (p == 0) {
-#pragma unroll
-    for (int k = 0; k < B; ++k) {
-      const int c = 8 * k + q;
-      const int pc = c < H ? c + H : c - H;
-      av[c] = c < m ? cscale(dcol[k], vp[pc & 63]) : czero();
-    }
-  }
   __syncthreads();
   for (int j = 0; j + 1 < n; ++j) {
-    // b_{j+1} = W b_j : row sums; lane needs b_j at its columns
-    cd xc[B], xr[B];
+    cd xc[B];
 #pragma unroll
     for (int k = 0; k < B; ++k) xc[k] = bv[64 * j + 8 * k + q];
 #pragma unroll
-    for (int a = 0; a < B; ++a) xr[a] = av[64 * j + 8 * a + p];
-    cd y[B], z[B];
-#pragma unroll
     for (int a = 0; a < B; ++a) {
-      y[a] = czero();
+      cd y = czero();
 #pragma unroll
-      for (int k = 0; k < B; ++k) y[a] = cfma(mk(Wr[a][k], Wi[a][k]), xc[k], y[a]);
-      y[a] = sum_row8(y[a]);
-    }
-    // alpha_{j+1} = W^T alpha_j : column sums; lane needs alpha_j at its rows
-#pragma unroll
-    for (int k = 0; k < B; ++k) {
-      z[k] = czero();
-#pragma unroll
-      for (int a = 0; a < B; ++a) z[k] = cfma(mk(Wr[a][k], Wi[a][k]), xr[a], z[k]);
-      z[k] = sum_col8(z[k]);
-    }
-    if (q == 0) {
-#pragma unroll
-      for (int a = 0; a < B; ++a) bv[64 * (j + 1) + 8 * a + p] = y[a];
-    }
-    if (p == 0) {
-#pragma unroll
-      for (int k = 0; k < B; ++k) av[64 * (j + 1) + 8 * k + q] = z[k];
+      for (int k = 0; k < B; ++k) y = cfma(mk(Wr[a][k], Wi[a][k]), xc[k], y);
+      y = sum_row8(y);
+      if (q == 0) bv[64 * (j + 1) + 8 * a + p] = y;
     }
     __syncthreads();
   }
-  // mu_k = sum_c u_c b_{k-1}[c], lanes over c
+  // mu_k = sum_c u_c b_{k-1}[c], u_c = d_{pair(c)} v_{partner(c)}
+  const int pl = lane < H ? lane + H : lane - H;
+  const cd ul = lane < m ? cscale(dlane, vp[pl & 63]) : czero();
   for (int k = 1; k <= n; ++k) {
-    double re = 0.0, im = 0.0;
-    if (lane < m) {
-      const cd t = cmul(av[lane], bv[64 * (k - 1) + lane]);
-      re = t.r;
-      im = t.i;
-    }
-    // full-wave sum: row groups then column groups
-    re = sum_col8(sum_row8(re));
-    im = sum_col8(sum_row8(im));
+    const cd t = cmul(ul, bv[64 * (k - 1) + lane]);
+    const double re = sum_col8(sum_row8(t.r));
+    const double im = sum_col8(sum_row8(t.i));
     if (lane == 0) L.mu[k] = mk(re, im);
   }
   __syncthreads();
@@ -164,7 +156,6 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
   const int m = P.m, H = P.H, n = P.n;
   cd* pw = scr;                          // [kMaxPS][LD*LD] powers W^1..W^s
   cd* bv = scr + kMaxPS * LD * LD;       // [33][64] b_j
-  cd* av = bv + 33 * 64;                 // [33][64] alpha_i
   cd* acoef = L.wb;                      // a_1..a_n (index k)
 
   // zero the item's accumulators
@@ -203,7 +194,7 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
 
     double Wr[B][B], Wi[B][B];
     load_w<B>(Cp, dcol, p, q, Wr, Wi);
-    krylov_pair<B>(Wr, Wi, dcol, vp, m, H, n, p, q, lane, bv, av, L);
+    krylov_b<B>(Wr, Wi, dlane, vp, m, H, n, p, q, lane, bv, L);
     spectral_series<B>(Wr, Wi, m, n, p, q, lane, L);
     // e_j = sum_k q_k L_{j-k};  a_k = e_{n-k} / 2 (k = 1..n)
     if (lane >= 1 && lane <= n) {
@@ -214,8 +205,11 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
     }
     __syncthreads();
 
-    // ---- P(W) = sum_{k=1..n} a_k W^{k-1} by Paterson-Stockmeyer
-    load_w<B>(Cp, dcol, p, q, Wr, Wi);
+    // ---- P(W) = sum_{k=1..n} a_k W^{k-1} by Paterson-Stockmeyer.  W is
+    // re-read from L2 (the pointer is hidden from the optimiser so it does
+    // not keep the first copy live through the Hessenberg phase).
+    const cd* Cp2 = launder_ptr(Cp);
+    load_w<B>(Cp2, dcol, p, q, Wr, Wi);
     store_mat<B>(Wr, Wi, pw, p, q);  // W^1
     __syncthreads();
     for (int e = 2; e <= s; ++e) {
@@ -226,29 +220,42 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
     // R = B_Q, then R <- R W^s + B_q for q = Q-1 .. 0, where
     // B_q = sum_{r=0..s-1} a_{qs+r+1} W^r
     double Rr[B][B], Ri[B][B];
+#pragma unroll
+    for (int a = 0; a < B; ++a)
+#pragma unroll
+      for (int k = 0; k < B; ++k) Rr[a][k] = Ri[a][k] = 0.0;
     for (int qq = Q; qq >= 0; --qq) {
       if (qq != Q) mul_right<B>(Rr, Ri, pw + (s - 1) * LD * LD, p, q);
+      // + a_{qs+1} I
+      {
+        const cd ak = acoef[qq * s + 1];
 #pragma unroll
-      for (int a = 0; a < B; ++a)
+        for (int a = 0; a < B; ++a)
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-          cd acc = qq == Q ? czero() : mk(Rr[a][k], Ri[a][k]);
-          const int i = 8 * a + p, c = 8 * k + q;
-          for (int r = 0; r < s; ++r) {
-            const int kk = qq * s + r + 1;
-            if (kk > n) break;
-            const cd ak = acoef[kk];
-            if (r == 0) {
-              if (i == c && i < m) acc = cadd(acc, ak);
-            } else {
-              acc = cfma(ak, pw[(r - 1) * LD * LD + i * LD + c], acc);
+          for (int k = 0; k < B; ++k) {
+            const int i = 8 * a + p, c = 8 * k + q;
+            if (i == c && i < m) {
+              Rr[a][k] += ak.r;
+              Ri[a][k] += ak.i;
             }
           }
-          Rr[a][k] = acc.r;
-          Ri[a][k] = acc.i;
-        }
+      }
+      // + sum_{r=1..s-1} a_{qs+r+1} W^r
+      for (int r = 1; r < s && qq * s + r + 1 <= n; ++r) {
+        const cd ak = acoef[qq * s + r + 1];
+        const cd* Pr = pw + (r - 1) * LD * LD;
+#pragma unroll
+        for (int a = 0; a < B; ++a)
+#pragma unroll
+          for (int k = 0; k < B; ++k) {
+            const cd o = cfma(ak, Pr[(8 * a + p) * LD + 8 * k + q], mk(Rr[a][k], Ri[a][k]));
+            Rr[a][k] = o.r;
+            Ri[a][k] = o.i;
+          }
+      }
     }
-    // ---- + sum_i beta_i alpha_i^T, beta_i = sum_j a_{i+j+2} b_j
+    // ---- + sum_i beta_i alpha_i^T, beta_i = sum_j a_{i+j+2} b_j,
+    //      alpha_i[c] = d_{pair(c)} b_i[partner(c)]
     for (int i = 0; i + 2 <= n; ++i) {
       cd beta[B], al[B];
 #pragma unroll
@@ -258,7 +265,11 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
         beta[a] = bsum;
       }
 #pragma unroll
-      for (int k = 0; k < B; ++k) al[k] = av[64 * i + 8 * k + q];
+      for (int k = 0; k < B; ++k) {
+        const int c = 8 * k + q;
+        const int pc = c < H ? c + H : c - H;
+        al[k] = cscale(dcol[k], bv[64 * i + (pc & 63)]);
+      }
 #pragma unroll
       for (int a = 0; a < B; ++a)
 #pragma unroll
@@ -268,33 +279,38 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
           Ri[a][k] = o.i;
         }
     }
-    // ---- accumulate c_t d_{pair(row)} M[row][col]
+    // ---- accumulate c_t d_{pair(row)} M[row][col] (pointer laundered so the
+    // loads are not hoisted above the products)
+    cd* Gl = const_cast<cd*>(launder_ptr(G));
 #pragma unroll
     for (int a = 0; a < B; ++a) {
       const double w = coef * drow[a];
 #pragma unroll
       for (int k = 0; k < B; ++k) {
-        cd* g = G + (8 * a + p) * LD + 8 * k + q;
+        cd* g = Gl + (8 * a + p) * LD + 8 * k + q;
         *g = cfma(mk(w, 0.0), mk(Rr[a][k], Ri[a][k]), *g);
       }
     }
     // ---- d f / d v_l = sum_k a_k (alpha_{k-1}[l] + d_{pair(l)} b_{k-1}[partner(l)])
+    //                  = 2 sum_k a_k d_{pair(l)} b_{k-1}[partner(l)]
     if (lane < m) {
       const int pl = lane < H ? lane + H : lane - H;
       cd gsum = czero();
-      for (int k = 1; k <= n; ++k) {
-        const cd x = cfma(mk(dlane, 0.0), bv[64 * (k - 1) + pl], av[64 * (k - 1) + lane]);
-        gsum = cfma(acoef[k], x, gsum);
-      }
-      G[LD * LD + lane] = cfma(mk(coef, 0.0), gsum, G[LD * LD + lane]);
+      for (int k = 1; k <= n; ++k) gsum = cfma(acoef[k], bv[64 * (k - 1) + pl], gsum);
+      G[LD * LD + lane] = cfma(mk(2.0 * coef * dlane, 0.0), gsum, G[LD * LD + lane]);
     }
     __syncthreads();
   }
 }
 
 template <int BMAX>
+#ifndef LH_BWD_WAVES
+#define LH_BWD_WAVES(bmax) ((bmax) <= 1 ? 4 : ((bmax) <= 3 ? 2 : 1))
+#endif
 #ifndef LH_BWD_ATTR
-#define LH_BWD_ATTR __launch_bounds__(64)
+#define LH_BWD_ATTR                   \
+  __launch_bounds__(64) __attribute__( \
+      (amdgpu_waves_per_eu(LH_BWD_WAVES(BMAX), LH_BWD_WAVES(BMAX))))
 #endif
 __global__ LH_BWD_ATTR void backward_kernel(const Prob* __restrict__ probs,
                                                       const Item* __restrict__ items, int n_items,
