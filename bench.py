@@ -1,18 +1,23 @@
 #!/usr/bin/env python
 """Loop-hafnian throughput on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload grad40] [--pass fwd|fwdbwd]
+    python bench.py [--steps K] [--warmup W] [--pass fwdbwd|fwd]
 
-A step is one pass of the hot path over one batch of synthetic input:
-the 256 N=40 Gaussian-state matrices of the differentiation workload
-(U Haar 40x40, r ~ U[0.5,1.5], gamma ~ CN(0,0.1)), finite-difference-sieve
-sum with double-double accumulation; with --pass fwdbwd the adjoint pass
-(d lhaf / dA, d lhaf / d gamma) runs too.  Inputs are resident in HBM before
-the timed region.  Prints one JSON line.
+A step is one pass of the hot path over one batch of synthetic input: the
+256 N=40 Gaussian-state matrices of the differentiation workload (U Haar
+40x40, r ~ U[0.5,1.5], gamma ~ CN(0,0.1)), finite-difference-sieve sum with
+double-double accumulation, forward (lhaf) and backward (d lhaf/dA,
+d lhaf/d gamma).  `value` is lhaf terms of the batch per second of the whole
+step (2^19 terms per matrix, each evaluated once forward and once in the
+adjoint).  Inputs are resident in HBM before the timed region.  One extra,
+untimed-for-value measurement runs a full N=52 block-diagonal lhaf (the
+paper's accuracy protocol) for the N=52 throughput and error.  Prints one
+JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import math
 import os
@@ -62,9 +67,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="grad40")
-    ap.add_argument("--pass", dest="passes", default="fwd", choices=["fwd", "fwdbwd"])
+    ap.add_argument("--pass", dest="passes", default="fwdbwd", choices=["fwd", "fwdbwd"])
+    ap.add_argument("--no-n52", action="store_true")
     ap.add_argument("--sum", default="fds", choices=["fds", "et"])
     ap.add_argument("--acc", default="dd", choices=["dd", "fp64"])
     ap.add_argument("--batch", type=int, default=256)
@@ -91,18 +97,28 @@ def main():
 
     fwd_ms, bwd_ms = [], []
     out = None
+    # workspaces allocated once, outside the timed region
+    off = np.arange(args.batch + 1, dtype=np.int64) * N
+    ws_fwd = torch.empty(api.lhaf_batched_workspace(off, sum=args.sum, acc=args.acc),
+                         dtype=torch.uint8, device=dev)
+    ws_bwd = None
+    ones = torch.ones(args.batch, dtype=torch.complex128, device=dev)
+    if args.passes == "fwdbwd":
+        nb = int(_binding.lib().lhaf_backward_workspace(args.batch, _binding.host_ptr(off), None, N,
+                                                         ctypes.byref(_binding.make_opts(args.sum, args.acc))))
+        ws_bwd = torch.empty(nb, dtype=torch.uint8, device=dev)
 
     def step(timed: bool):
         nonlocal out
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        out = api.lhaf_batched(A, g, sum=args.sum, acc=args.acc)
+        out = api.lhaf_batched(A, g, sum=args.sum, acc=args.acc, workspace=ws_fwd)
         e1.record(stream)
         if args.passes == "fwdbwd":
             e2 = torch.cuda.Event(enable_timing=True)
             e2.record(stream)
-            api.lhaf_backward(A, g, torch.ones_like(out), sum=args.sum, acc=args.acc)
+            api.lhaf_backward(A, g, ones, sum=args.sum, acc=args.acc, workspace=ws_bwd)
             e3 = torch.cuda.Event(enable_timing=True)
             e3.record(stream)
         if timed:
@@ -125,12 +141,24 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
 
     passes = 2 if args.passes == "fwdbwd" else 1
-    value = passes * terms * args.steps / elapsed
+    value = terms * args.steps / elapsed
     fwd_s = np.mean(fwd_ms) / 1e3
-    achieved = canonical_flops(m, n) * terms / fwd_s / 1e12
+    fwd_tf = canonical_flops(m, n) * terms / fwd_s / 1e12
+    if bwd_ms:
+        bwd_s = np.mean(bwd_ms) / 1e3
+        bwd_tf = canonical_flops_bwd(m, n) * terms / bwd_s / 1e12
+        dom = {"bound": "alu", "kernel": "backward_kernel<5>", "achieved": bwd_tf,
+               "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": bwd_tf / FP64_PEAK_TFLOPS,
+               "traffic": None, "per_term_flops": canonical_flops_bwd(m, n),
+               "terms_per_launch": terms, "launch_ms": bwd_s * 1e3}
+    else:
+        dom = {"bound": "alu", "kernel": "forward_kernel<5>", "achieved": fwd_tf,
+               "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": fwd_tf / FP64_PEAK_TFLOPS,
+               "traffic": None, "per_term_flops": canonical_flops(m, n),
+               "terms_per_launch": terms, "launch_ms": fwd_s * 1e3}
     res = {
-        "metric": "lhaf terms/sec (FDS, N=40 Gaussian-state batch of 256; "
-                  + ("forward" if passes == 1 else "forward + backward") + ")",
+        "metric": "lhaf terms/sec (N=40, FDS, double-double; " +
+                  ("forward + backward" if passes == 2 else "forward") + ")",
         "value": value,
         "unit": "terms/s",
         "n_gpus": 1,
@@ -143,19 +171,18 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded Gaussian-state matrices)",
         "config": {"workload": f"grad40: {args.batch} x lhaf N={N} complex128, {args.sum.upper()} "
-                               f"{args.acc} accumulation, " + ("fwd" if passes == 1 else "fwd+bwd"),
+                               f"{args.acc} accumulation, " + ("fwd+bwd" if passes == 2 else "fwd"),
                    "global_batch": args.batch, "N": N, "terms_per_lhaf": terms_per_problem,
                    "sum": args.sum, "acc": args.acc},
-        "roofline": {"bound": "alu", "kernel": "forward_kernel",
-                     "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "per_term_flops": canonical_flops(m, n), "launch_ms": fwd_s * 1e3},
-        "fwd_terms_per_s": terms / fwd_s,
+        "roofline": dom,
+        "forward": {"kernel": "forward_kernel<5>", "terms_per_s": terms / fwd_s, "tflops": fwd_tf,
+                    "frac": fwd_tf / FP64_PEAK_TFLOPS, "launch_ms": fwd_s * 1e3,
+                    "per_term_flops": canonical_flops(m, n)},
     }
     if bwd_ms:
-        bwd_s = np.mean(bwd_ms) / 1e3
-        res["bwd_terms_per_s"] = terms / bwd_s
-        res["bwd_tflops"] = canonical_flops_bwd(m, n) * terms / bwd_s / 1e12
+        res["backward"] = {"kernel": "backward_kernel<5>", "terms_per_s": terms / bwd_s,
+                           "tflops": bwd_tf, "frac": bwd_tf / FP64_PEAK_TFLOPS,
+                           "launch_ms": bwd_s * 1e3, "per_term_flops": canonical_flops_bwd(m, n)}
     # relative error against stored oracle values (tests/golden, oracle-only)
     gold_path = os.path.join(ROOT, "tests", "golden", "oracle_values.json")
     if os.path.exists(gold_path) and args.sum == "fds":
@@ -171,6 +198,32 @@ def main():
         if errs:
             res["rel_err_vs_oracle"] = {"max": max(errs), "count": len(errs),
                                         "oracle": "FDS double, explicit matrix powers"}
+    if not args.no_n52:
+        # N = 52 forward: one full block-diagonal lhaf (2^25 terms, tile B = 7)
+        A52, g52, _, _ = inputs.block_diagonal_stress(52, 0)
+        a52 = torch.as_tensor(A52, device=dev)
+        q52 = torch.as_tensor(g52, device=dev)
+        api.lhaf(a52, q52)  # warm
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        v52 = api.lhaf(a52, q52)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t52 = e0.elapsed_time(e1) / 1e3
+        T52 = _binding.term_count(52)
+        tf52 = canonical_flops(52, 26) * T52 / t52 / 1e12
+        ent = {"workload": "block52/0 (A1 (+) A2, N=52, FDS dd)", "terms_per_s": T52 / t52,
+               "tflops": tf52, "frac": tf52 / FP64_PEAK_TFLOPS, "seconds": t52}
+        if os.path.exists(gold_path):
+            gold = json.load(open(gold_path))
+            if "block52/0" in gold:
+                ref = complex(*gold["block52/0"]["value"])
+                ent["rel_err_vs_oracle"] = abs(v52.item() - ref) / abs(ref)
+                ent["oracle"] = "__float128 FDS of both halves, multiplied"
+        res["n52_forward"] = ent
+        print("[bench] N=52 done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(A_np[0], g_np[0])
     print(json.dumps(res), flush=True)
