@@ -71,6 +71,9 @@ def main():
     ap.add_argument("--workload", default="grad40")
     ap.add_argument("--pass", dest="passes", default="fwdbwd", choices=["fwd", "fwdbwd"])
     ap.add_argument("--no-n52", action="store_true")
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="run one plain device copy of this size before timing (a known-size "
+                         "reference for memory-traffic counters)")
     ap.add_argument("--sum", default="fds", choices=["fds", "et"])
     ap.add_argument("--acc", default="dd", choices=["dd", "fp64"])
     ap.add_argument("--batch", type=int, default=256)
@@ -95,6 +98,12 @@ def main():
     terms = args.batch * terms_per_problem
     stream = torch.cuda.current_stream(dev)
 
+    if args.copy_ref_mib > 0:
+        src = torch.ones(args.copy_ref_mib * (1 << 17), dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     fwd_ms, bwd_ms = [], []
     out = None
     # workspaces allocated once, outside the timed region

@@ -83,6 +83,13 @@ __device__ __forceinline__ double sum_col8(double x) {
   x = sum_xor32(x);
   return x;
 }
+// sum over each half-wave (lanes 0..31 and 32..63 separately)
+__device__ __forceinline__ double sum_half32(double x) {
+  x = sum_row8(x);
+  x += dpp_d<0x128>(x);  // row_ror:8
+  return sum_xor16(x);
+}
+__device__ __forceinline__ cd sum_half32(cd a) { return mk(sum_half32(a.r), sum_half32(a.i)); }
 __device__ __forceinline__ cd sum_row8(cd a) { return mk(sum_row8(a.r), sum_row8(a.i)); }
 __device__ __forceinline__ cd sum_col8(cd a) { return mk(sum_col8(a.r), sum_col8(a.i)); }
 __device__ __forceinline__ cd sum_xor32(cd a) { return mk(sum_xor32(a.r), sum_xor32(a.i)); }

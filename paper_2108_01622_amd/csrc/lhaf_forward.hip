@@ -196,15 +196,23 @@ __device__ __forceinline__ void charpoly_step(const double (&Wr)[B][B], const do
   __syncthreads();
   const int t = (lane & 31) + 1;
   const int slot = lane >> 5;
-  cd acc = czero();
+  cd acc = czero(), acc2 = czero();
   if (t <= n) {
     const int ilo = (J + 1 - t) > 0 ? (J + 1 - t) : 0;
-    for (int i = J - 1 - slot; i >= ilo; i -= 2) {
+    int i = J - 1 - slot;
+    // two independent chains so the LDS loads of one overlap the other's FMAs
+    for (; i - 2 >= ilo; i -= 4) {
+      const cd* Tp = L.ring + ring_slot(i - 1, L.NR) * L.NP;
+      const cd* Tq = L.ring + ring_slot(i - 3, L.NR) * L.NP;
+      acc = cfma(L.wb[i], Tp[t - (J - i + 1)], acc);
+      acc2 = cfma(L.wb[i - 2], Tq[t - (J - i + 3)], acc2);
+    }
+    if (i >= ilo) {
       const cd* Tp = L.ring + ring_slot(i - 1, L.NR) * L.NP;
       acc = cfma(L.wb[i], Tp[t - (J - i + 1)], acc);
     }
   }
-  acc = sum_xor32(acc);
+  acc = sum_xor32(cadd(acc, acc2));
   const cd* Tprev = L.ring + ring_slot(J - 1, L.NR) * L.NP;
   cd* Tcur = L.ring + ring_slot(J, L.NR) * L.NP;
   cd val = czero();
@@ -393,20 +401,24 @@ __device__ __forceinline__ void spectral_series(double (&Wr)[B][B], double (&Wi)
   __syncthreads();
   cd pi = czero(), hsub = czero();
   HessLoop<B, 0>::run(Wr, Wi, m, n, p, q, lane, pi, hsub, L);
+  // Both series at once: lanes 0..31 build q, lanes 32..63 build L.  Step k
+  // is a 32-lane dot product over j = 1..k (lane j-1 of the half) reduced by
+  // a butterfly inside the half, so the serial chain is n steps long.
   const cd* cpoly = L.ring + ring_slot(m - 1, L.NR) * L.NP;
-  if (lane < 2) {
-    const cd* xs = lane == 0 ? cpoly : L.mu;
-    cd* ys = L.ser + 33 * lane;
-    const double al = lane == 0 ? -1.0 : 0.0;
-    ys[0] = mk(1.0, 0.0);
-    for (int k = 1; k <= n; ++k) {
-      cd s = czero();
-      for (int jx = 1; jx <= k; ++jx)
-        s = cfma(cscale(fma(al, (double)k, 0.5 * jx), xs[jx]), ys[k - jx], s);
-      ys[k] = cscale(1.0 / k, s);
-    }
-  }
+  const int h = lane >> 5, j = (lane & 31) + 1;
+  const cd* xs = h == 0 ? cpoly : L.mu;
+  cd* ys = L.ser + 33 * h;
+  const cd xj = j <= n ? xs[j] : czero();
+  const double al = h == 0 ? -1.0 : 0.0;
+  if ((lane & 31) == 0) ys[0] = mk(1.0, 0.0);
   __syncthreads();
+  for (int k = 1; k <= n; ++k) {
+    cd t = czero();
+    if (j <= k) t = cmul(cscale(fma(al, (double)k, 0.5 * j), xj), ys[k - j]);
+    t = sum_half32(t);
+    if ((lane & 31) == 0) ys[k] = cscale(1.0 / k, t);
+    __syncthreads();
+  }
 }
 
 // -------------------------------------------------------------------------
@@ -437,9 +449,10 @@ __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const 
     load_w<B>(Cp, dcol, p, q, Wr, Wi);
     loop_moments<B>(Wr, Wi, dcol, vp, m, H, n, p, q, lane, L);
     spectral_series<B>(Wr, Wi, m, n, p, q, lane, L);
-    // every lane forms f and accumulates the same value (wave-uniform loop tail)
+    // f = sum_k q_k L_{n-k}: lanes over k, full-wave sum (every lane gets f)
     cd f = czero();
-    for (int k = 0; k <= n; ++k) f = cfma(L.ser[k], L.ser[33 + n - k], f);
+    if (lane <= n) f = cmul(L.ser[lane], L.ser[33 + n - lane]);
+    f = mk(sum_col8(sum_row8(f.r)), sum_col8(sum_row8(f.i)));
     if (acc_dd) {
       dd_add_prod(accr, coef, f.r);
       dd_add_prod(acci, coef, f.i);
