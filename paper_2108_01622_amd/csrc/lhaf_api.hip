@@ -165,7 +165,7 @@ struct Plan {
 
 // wavefronts of one kernel instance resident per CU (occupancy query)
 int resident_per_cu(bool bwd, int bmax, int nmax) {
-  const size_t lds = lds_bytes_for(std::max(nmax, 1));
+  const size_t lds = bwd ? bwd_lds_bytes(bmax, std::max(nmax, 1)) : lds_bytes_for(std::max(nmax, 1));
   const void* fn = nullptr;
   switch (bmax) {
 #define LH_FN(BB)                                                                      \
@@ -654,7 +654,7 @@ static lh_status backward_impl(int32_t B, const lh_c128* A_base, int64_t lda, in
   cd* gsl = reinterpret_cast<cd*>(base + off_g);
   cd* scratch = reinterpret_cast<cd*>(base + off_s);
   if (!pl.items.empty()) {
-    const size_t lds = lds_bytes_for(std::max(pl.nmax, 1));
+    const size_t lds = bwd_lds_bytes(pl.bmax, std::max(pl.nmax, 1));
 #define LH_BLAUNCH(BB)                                                                          \
   hipLaunchKernelGGL(HIP_KERNEL_NAME(backward_kernel<BB>), dim3(pl.grid), dim3(64), lds, st,    \
                      reinterpret_cast<const Prob*>(base + pl.lay.probs),                        \

@@ -13,12 +13,18 @@
 // P(W) is evaluated by Paterson-Stockmeyer (s = ceil(sqrt n): powers
 // W^1..W^s, then Horner in W^s), the dense contraction of this path; the
 // products keep one operand in registers (8 x 8 lane grid, row broadcasts by
-// ds_bpermute) and stream the other from a per-wavefront scratch in global
-// memory.  Terms are recomputed per subset; nothing is stored across terms
-// except the running gradient of the item.
+// ds_bpermute) and stream the other.  For register tiles B <= kStageMaxB the
+// streamed operand (W while the powers are formed, then W^s) and the Krylov
+// vectors live in a per-wavefront LDS region X, so the products and the
+// rank-one terms never wait on global memory; the powers that the Horner
+// steps combine elementwise go to a per-wavefront scratch in global memory.
+// Larger tiles (whose LDS share would cut occupancy) keep everything in the
+// global scratch.  Terms are recomputed per subset; nothing is stored across
+// terms except the running gradient of the item.
 namespace lh {
 
-constexpr int kMaxPS = 6;  // ceil(sqrt(32))
+constexpr int kMaxPS = 6;      // ceil(sqrt(32))
+constexpr int kStageMaxB = 5;  // largest register tile with LDS staging
 
 // The same address as p, opaque to the optimiser (forces a fresh load).
 template <class T>
@@ -36,11 +42,24 @@ __host__ __device__ inline size_t bwd_item_elems(int B) {
   const size_t LD = 8 * (size_t)B;
   return LD * LD + 64;
 }
+// complex elements of the LDS region X of a backward kernel instance (0
+// without staging): the larger of one LD x LD matrix and nmax Krylov vectors
+// of LD entries.
+__host__ __device__ inline size_t bwd_x_elems(int bmax, int nmax) {
+  if (bmax > kStageMaxB) return 0;
+  const size_t LD = 8 * (size_t)bmax;
+  return LD * (LD > (size_t)nmax ? LD : (size_t)nmax);
+}
+inline size_t bwd_lds_bytes(int bmax, int nmax) {
+  return lds_bytes_for(nmax) + sizeof(cd) * bwd_x_elems(bmax, nmax);
+}
+// X starts after the forward layout (16-byte aligned)
+__device__ __forceinline__ cd* lds_x(const LdsView& L) { return L.ring + L.NP * L.NR; }
 
 // R <- R * M with R in registers (lane (p,q) holds R[8a+p][8k+q]) and M
-// row-major LD x LD in global memory (L2 resident).  Output row i needs only
-// input row i, so rows are done in groups of G local rows, in place: only the
-// group's accumulators are live, and M is streamed once per group.
+// row-major LD x LD (LDS or global).  Output row i needs only input row i,
+// so rows are done in groups of G local rows, in place: only the group's
+// accumulators are live, and M is streamed once per group.
 template <int B, int G, int A0>
 __device__ __forceinline__ void mul_rows(double (&Rr)[B][B], double (&Ri)[B][B],
                                          const cd* __restrict__ M, const int p, const int q) {
@@ -103,30 +122,31 @@ __device__ __forceinline__ void store_mat(const double (&Rr)[B][B], const double
     for (int k = 0; k < B; ++k) M[(8 * a + p) * LD + 8 * k + q] = mk(Rr[a][k], Ri[a][k]);
 }
 
-// Krylov sequence b_j = W^j v (0 <= j < n) in the wavefront scratch (row
-// index = vertex) and the loop moments mu_k = u . b_{k-1} (u = X_d v) into
-// L.mu.  The second sequence alpha_i = (W^T)^i u needs no products: X_d W is
-// symmetric, so (W^T)^i X_d = X_d W^i and alpha_i = X_d b_i, i.e.
+// Krylov sequence b_j = W^j v (0 <= j < n) into bv (vector j at bv + S j,
+// entry = vertex; rows up to 8B are written, zero beyond m) and the loop
+// moments mu_k = u . b_{k-1} (u = X_d v) into L.mu.  The second sequence
+// alpha_i = (W^T)^i u needs no products: X_d W is symmetric, so
+// (W^T)^i X_d = X_d W^i and alpha_i = X_d b_i, i.e.
 // alpha_i[c] = d_{pair(c)} b_i[partner(c)].
-template <int B>
+template <int B, int S>
 __device__ __forceinline__ void krylov_b(const double (&Wr)[B][B], const double (&Wi)[B][B],
                                          const double dlane, const cd* __restrict__ vp,
                                          const int m, const int H, const int n, const int p,
                                          const int q, const int lane, cd* __restrict__ bv,
                                          LdsView& L) {
-  bv[lane] = vp[lane];
+  if (lane < 8 * B) bv[lane] = vp[lane];
   __syncthreads();
   for (int j = 0; j + 1 < n; ++j) {
     cd xc[B];
 #pragma unroll
-    for (int k = 0; k < B; ++k) xc[k] = bv[64 * j + 8 * k + q];
+    for (int k = 0; k < B; ++k) xc[k] = bv[S * j + 8 * k + q];
 #pragma unroll
     for (int a = 0; a < B; ++a) {
       cd y = czero();
 #pragma unroll
       for (int k = 0; k < B; ++k) y = cfma(mk(Wr[a][k], Wi[a][k]), xc[k], y);
       y = sum_row8(y);
-      if (q == 0) bv[64 * (j + 1) + 8 * a + p] = y;
+      if (q == 0) bv[S * (j + 1) + 8 * a + p] = y;
     }
     __syncthreads();
   }
@@ -134,7 +154,7 @@ __device__ __forceinline__ void krylov_b(const double (&Wr)[B][B], const double 
   const int pl = lane < H ? lane + H : lane - H;
   const cd ul = lane < m ? cscale(dlane, vp[pl & 63]) : czero();
   for (int k = 1; k <= n; ++k) {
-    const cd t = cmul(ul, bv[64 * (k - 1) + lane]);
+    const cd t = lane < m ? cmul(ul, bv[S * (k - 1) + lane]) : czero();
     const double re = sum_col8(sum_row8(t.r));
     const double im = sum_col8(sum_row8(t.i));
     if (lane == 0) L.mu[k] = mk(re, im);
@@ -142,21 +162,84 @@ __device__ __forceinline__ void krylov_b(const double (&Wr)[B][B], const double 
   __syncthreads();
 }
 
+// R += sum_{i+j <= n-2} a_{i+j+2} b_j alpha_i^T = sum_i beta_i alpha_i^T with
+// beta_i = sum_j a_{i+j+2} b_j (each lane forms beta_i at its own vertex and
+// the grid reads it back through the LDS buffer xb).
+template <int B, int S>
+__device__ __forceinline__ void rank_terms(double (&Rr)[B][B], double (&Ri)[B][B],
+                                           const cd* __restrict__ bv, const cd* __restrict__ acoef,
+                                           const double (&dcol)[B], const int m, const int H,
+                                           const int n, const int p, const int q,
+                                           const int lane, cd* __restrict__ xb) {
+  for (int i = 0; i + 2 <= n; ++i) {
+    cd b0 = czero(), b1 = czero();
+    if (lane < m) {
+      int j = 0;
+      for (; i + j + 3 <= n; j += 2) {
+        b0 = cfma(acoef[i + j + 2], bv[S * j + lane], b0);
+        b1 = cfma(acoef[i + j + 3], bv[S * (j + 1) + lane], b1);
+      }
+      if (i + j + 2 <= n) b0 = cfma(acoef[i + j + 2], bv[S * j + lane], b0);
+    }
+    cd* bb = xb + 64 * (i & 1);
+    bb[lane] = cadd(b0, b1);
+    __syncthreads();
+    cd beta[B], al[B];
+#pragma unroll
+    for (int a = 0; a < B; ++a) beta[a] = bb[8 * a + p];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const int c = 8 * k + q;
+      const int pc = c < H ? c + H : c - H;
+      al[k] = c < m ? cscale(dcol[k], bv[S * i + pc]) : czero();
+    }
+#pragma unroll
+    for (int a = 0; a < B; ++a)
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const cd o = cfma(beta[a], al[k], mk(Rr[a][k], Ri[a][k]));
+        Rr[a][k] = o.r;
+        Ri[a][k] = o.i;
+      }
+  }
+}
+
+// G[row][col] += w_row R[row][col] (pointer laundered so the loads are not
+// hoisted above the computation of R)
+template <int B>
+__device__ __forceinline__ void accumulate_g(cd* __restrict__ G, const double coef,
+                                             const double (&drow)[B], const double (&Rr)[B][B],
+                                             const double (&Ri)[B][B], const int p, const int q) {
+  constexpr int LD = 8 * B;
+  cd* Gl = const_cast<cd*>(launder_ptr(G));
+#pragma unroll
+  for (int a = 0; a < B; ++a) {
+    const double w = coef * drow[a];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      cd* g = Gl + (8 * a + p) * LD + 8 * k + q;
+      *g = cfma(mk(w, 0.0), mk(Rr[a][k], Ri[a][k]), *g);
+    }
+  }
+}
+
 // Gradient of the terms [t0, t1) of problem P into the item slot
 // G[LD*LD] (accumulated as sum_t c_t d_{pair(j)} M_t[j][c], M = (d f/d W)^T)
 // and G[LD*LD + l] (d f / d v_l).
-template <int B>
+template <int B, bool kStage>
 __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, const int64_t t1,
                                              const cd* __restrict__ Cp,
                                              const cd* __restrict__ vp, cd* __restrict__ G,
                                              cd* __restrict__ scr, LdsView& L) {
   constexpr int LD = 8 * B;
+  constexpr int S = kStage ? LD : 64;    // stride of the Krylov vectors
   const int lane = threadIdx.x & 63;
   const int p = lane >> 3, q = lane & 7;
   const int m = P.m, H = P.H, n = P.n;
-  cd* pw = scr;                          // [kMaxPS][LD*LD] powers W^1..W^s
-  cd* bv = scr + kMaxPS * LD * LD;       // [33][64] b_j
-  cd* acoef = L.wb;                      // a_1..a_n (index k)
+  cd* pw = scr;                                          // [kMaxPS][LD*LD] powers
+  cd* X = lds_x(L);                                      // staging region (kStage)
+  cd* bv = kStage ? X : scr + kMaxPS * LD * LD;          // Krylov vectors
+  cd* acoef = L.wb;                                      // a_1..a_n (index k)
 
   // zero the item's accumulators
 #pragma unroll
@@ -194,7 +277,7 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
 
     double Wr[B][B], Wi[B][B];
     load_w<B>(Cp, dcol, p, q, Wr, Wi);
-    krylov_b<B>(Wr, Wi, dlane, vp, m, H, n, p, q, lane, bv, L);
+    krylov_b<B, S>(Wr, Wi, dlane, vp, m, H, n, p, q, lane, bv, L);
     spectral_series<B>(Wr, Wi, m, n, p, q, lane, L);
     // e_j = sum_k q_k L_{j-k};  a_k = e_{n-k} / 2 (k = 1..n)
     if (lane >= 1 && lane <= n) {
@@ -205,27 +288,54 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
     }
     __syncthreads();
 
+    double Rr[B][B], Ri[B][B];
+    // ---- rank-one terms sum_i beta_i alpha_i^T (while the Krylov vectors
+    // are resident), added to the item gradient ahead of P(W)
+#pragma unroll
+    for (int a = 0; a < B; ++a)
+#pragma unroll
+      for (int k = 0; k < B; ++k) Rr[a][k] = Ri[a][k] = 0.0;
+    rank_terms<B, S>(Rr, Ri, bv, acoef, dcol, m, H, n, p, q, lane, L.xb);
+    accumulate_g<B>(G, coef, drow, Rr, Ri, p, q);
+    // ---- d f / d v_l = sum_k a_k (alpha_{k-1}[l] + d_{pair(l)} b_{k-1}[partner(l)])
+    //                  = 2 sum_k a_k d_{pair(l)} b_{k-1}[partner(l)]
+    if (lane < m) {
+      const int pl = lane < H ? lane + H : lane - H;
+      cd g0 = czero(), g1 = czero();
+      int k = 1;
+      for (; k + 1 <= n; k += 2) {
+        g0 = cfma(acoef[k], bv[S * (k - 1) + pl], g0);
+        g1 = cfma(acoef[k + 1], bv[S * k + pl], g1);
+      }
+      if (k <= n) g0 = cfma(acoef[k], bv[S * (k - 1) + pl], g0);
+      G[LD * LD + lane] = cfma(mk(2.0 * coef * dlane, 0.0), cadd(g0, g1), G[LD * LD + lane]);
+    }
+    __syncthreads();
+
     // ---- P(W) = sum_{k=1..n} a_k W^{k-1} by Paterson-Stockmeyer.  W is
     // re-read from L2 (the pointer is hidden from the optimiser so it does
     // not keep the first copy live through the Hessenberg phase).
     const cd* Cp2 = launder_ptr(Cp);
     load_w<B>(Cp2, dcol, p, q, Wr, Wi);
-    store_mat<B>(Wr, Wi, pw, p, q);  // W^1
+    if (kStage) store_mat<B>(Wr, Wi, X, p, q);
+    if (s > 1) store_mat<B>(Wr, Wi, pw, p, q);  // W^1
     __syncthreads();
+    const cd* Wop = kStage ? X : pw;
+    cd* Yop = kStage ? X : pw + (s - 1) * LD * LD;
     for (int e = 2; e <= s; ++e) {
-      mul_right<B>(Wr, Wi, pw, p, q);  // W^e = W^{e-1} W
-      store_mat<B>(Wr, Wi, pw + (e - 1) * LD * LD, p, q);
+      mul_right<B>(Wr, Wi, Wop, p, q);  // W^e = W^{e-1} W
+      if (e == s) __syncthreads();      // every read of W precedes its overwrite
+      store_mat<B>(Wr, Wi, e < s ? pw + (e - 1) * LD * LD : Yop, p, q);
       __syncthreads();
     }
     // R = B_Q, then R <- R W^s + B_q for q = Q-1 .. 0, where
     // B_q = sum_{r=0..s-1} a_{qs+r+1} W^r
-    double Rr[B][B], Ri[B][B];
 #pragma unroll
     for (int a = 0; a < B; ++a)
 #pragma unroll
       for (int k = 0; k < B; ++k) Rr[a][k] = Ri[a][k] = 0.0;
     for (int qq = Q; qq >= 0; --qq) {
-      if (qq != Q) mul_right<B>(Rr, Ri, pw + (s - 1) * LD * LD, p, q);
+      if (qq != Q) mul_right<B>(Rr, Ri, Yop, p, q);
       // + a_{qs+1} I
       {
         const cd ak = acoef[qq * s + 1];
@@ -240,65 +350,32 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
             }
           }
       }
-      // + sum_{r=1..s-1} a_{qs+r+1} W^r
-      for (int r = 1; r < s && qq * s + r + 1 <= n; ++r) {
-        const cd ak = acoef[qq * s + r + 1];
-        const cd* Pr = pw + (r - 1) * LD * LD;
+      // + sum_{r=1..s-1} a_{qs+r+1} W^r, two powers per batch of loads
+      for (int r = 1; r < s && qq * s + r + 1 <= n; r += 2) {
+        const bool two = r + 1 < s && qq * s + r + 2 <= n;
+        const cd a1 = acoef[qq * s + r + 1];
+        const cd a2 = two ? acoef[qq * s + r + 2] : czero();
+        const cd* P1 = pw + (r - 1) * LD * LD;
+        const cd* P2 = two ? P1 + LD * LD : P1;
+        cd x1[B][B], x2[B][B];
 #pragma unroll
         for (int a = 0; a < B; ++a)
 #pragma unroll
           for (int k = 0; k < B; ++k) {
-            const cd o = cfma(ak, Pr[(8 * a + p) * LD + 8 * k + q], mk(Rr[a][k], Ri[a][k]));
+            x1[a][k] = P1[(8 * a + p) * LD + 8 * k + q];
+            x2[a][k] = P2[(8 * a + p) * LD + 8 * k + q];
+          }
+#pragma unroll
+        for (int a = 0; a < B; ++a)
+#pragma unroll
+          for (int k = 0; k < B; ++k) {
+            const cd o = cfma(a2, x2[a][k], cfma(a1, x1[a][k], mk(Rr[a][k], Ri[a][k])));
             Rr[a][k] = o.r;
             Ri[a][k] = o.i;
           }
       }
     }
-    // ---- + sum_i beta_i alpha_i^T, beta_i = sum_j a_{i+j+2} b_j,
-    //      alpha_i[c] = d_{pair(c)} b_i[partner(c)]
-    for (int i = 0; i + 2 <= n; ++i) {
-      cd beta[B], al[B];
-#pragma unroll
-      for (int a = 0; a < B; ++a) {
-        cd bsum = czero();
-        for (int j = 0; i + j + 2 <= n; ++j) bsum = cfma(acoef[i + j + 2], bv[64 * j + 8 * a + p], bsum);
-        beta[a] = bsum;
-      }
-#pragma unroll
-      for (int k = 0; k < B; ++k) {
-        const int c = 8 * k + q;
-        const int pc = c < H ? c + H : c - H;
-        al[k] = cscale(dcol[k], bv[64 * i + (pc & 63)]);
-      }
-#pragma unroll
-      for (int a = 0; a < B; ++a)
-#pragma unroll
-        for (int k = 0; k < B; ++k) {
-          const cd o = cfma(beta[a], al[k], mk(Rr[a][k], Ri[a][k]));
-          Rr[a][k] = o.r;
-          Ri[a][k] = o.i;
-        }
-    }
-    // ---- accumulate c_t d_{pair(row)} M[row][col] (pointer laundered so the
-    // loads are not hoisted above the products)
-    cd* Gl = const_cast<cd*>(launder_ptr(G));
-#pragma unroll
-    for (int a = 0; a < B; ++a) {
-      const double w = coef * drow[a];
-#pragma unroll
-      for (int k = 0; k < B; ++k) {
-        cd* g = Gl + (8 * a + p) * LD + 8 * k + q;
-        *g = cfma(mk(w, 0.0), mk(Rr[a][k], Ri[a][k]), *g);
-      }
-    }
-    // ---- d f / d v_l = sum_k a_k (alpha_{k-1}[l] + d_{pair(l)} b_{k-1}[partner(l)])
-    //                  = 2 sum_k a_k d_{pair(l)} b_{k-1}[partner(l)]
-    if (lane < m) {
-      const int pl = lane < H ? lane + H : lane - H;
-      cd gsum = czero();
-      for (int k = 1; k <= n; ++k) gsum = cfma(acoef[k], bv[64 * (k - 1) + pl], gsum);
-      G[LD * LD + lane] = cfma(mk(2.0 * coef * dlane, 0.0), gsum, G[LD * LD + lane]);
-    }
+    accumulate_g<B>(G, coef, drow, Rr, Ri, p, q);
     __syncthreads();
   }
 }
@@ -333,7 +410,7 @@ __global__ LH_BWD_ATTR void backward_kernel(const Prob* __restrict__ probs,
     switch (P.B) {
 #define LH_BCASE(BB)                                                                   \
   case BB:                                                                             \
-    if (BB <= BMAX) run_item_bwd<(BB <= BMAX ? BB : 1)>(P, I.t0, I.t1, Cp, vp, G, scr, L); \
+    if (BB <= BMAX) run_item_bwd<(BB <= BMAX ? BB : 1), (BMAX <= kStageMaxB)>(P, I.t0, I.t1, Cp, vp, G, scr, L); \
     break;
       LH_BCASE(1)
       LH_BCASE(2)
