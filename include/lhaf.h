@@ -80,6 +80,17 @@ typedef struct {
   size_t ws_bytes;
   lh_c128* out_lo;    /* nullable device array: low parts of the double-double
                          results (out holds the high parts) */
+  lh_c128* saved;     /* nullable device array of lhaf_saved_count() per-term
+                         series coefficients shared by one lhaf_batched call and
+                         the lhaf_backward call on the same batch and sum mode:
+                         the forward writes a_k = e_{n-k}/2 (k = 1..n, e_j the
+                         lambda^j coefficient of exp(sum_k g_k lambda^k)) of
+                         every term, the backward reads them instead of
+                         repeating the Hessenberg reduction.  Problem b's block
+                         starts after the blocks of problems < b; term t's
+                         entries start at t*n_b inside it.  The forward needs the
+                         full term range.  The backward trusts the contents. */
+  int64_t saved_count; /* entries available at saved */
 } lh_opts;
 
 /* Term enumeration (identical for every entry point).  Pairs p = 0..H-1 with
@@ -138,6 +149,11 @@ lh_status lhaf_batched(int32_t B, const lh_c128* A_base, int64_t lda, int64_t st
                        const lh_c128* gamma_base, int64_t stride_g, const int32_t* idx,
                        const int64_t* idx_off, const int32_t* r, lh_c128* out, double* err_est,
                        void* workspace, size_t ws_bytes, const lh_opts* opts, void* stream);
+
+/* Entries (lh_c128) of the per-term coefficient store of the batch for
+ * opts->sum: sum over problems of terms x n.  Host only; a negative value is
+ * -lh_status. */
+int64_t lhaf_saved_count(int32_t B, const int64_t* idx_off, const int32_t* r, const lh_opts* opts);
 
 /* Gradients of the batch above (the paper has none; adjoint of the per-term
  * power-trace recursion).  Holomorphic derivative, returned in PyTorch's

@@ -31,6 +31,8 @@ class LhOpts(ctypes.Structure):
         ("workspace", ctypes.c_void_p),
         ("ws_bytes", ctypes.c_size_t),
         ("out_lo", ctypes.c_void_p),
+        ("saved", ctypes.c_void_p),
+        ("saved_count", ctypes.c_int64),
     ]
 
 
@@ -71,6 +73,8 @@ def lib():
         L.lhaf_batched.argtypes = [i32, vp, i64, i64, vp, i64, vp, vp, vp, vp, vp, vp, sz,
                                    P(LhOpts), vp]
         L.lhaf_batched.restype = i32
+        L.lhaf_saved_count.argtypes = [i32, vp, vp, P(LhOpts)]
+        L.lhaf_saved_count.restype = i64
         L.lhaf_backward_workspace.argtypes = [i32, vp, vp, i32, P(LhOpts)]
         L.lhaf_backward_workspace.restype = sz
         L.lhaf_backward.argtypes = [i32, vp, i64, i64, vp, i64, vp, vp, vp, vp, vp, vp, i32, vp,
@@ -82,7 +86,7 @@ def lib():
 
 EXPORTED = ["lh_opts_default", "lh_status_string", "lhaf_schedule_count", "lhaf_term_count",
             "lhaf_plan_pairs", "lhaf", "lhaf_repeated", "lhaf_batched_workspace", "lhaf_batched",
-            "lhaf_backward_workspace", "lhaf_backward"]
+            "lhaf_saved_count", "lhaf_backward_workspace", "lhaf_backward"]
 
 
 def check(status: int) -> None:
@@ -91,7 +95,7 @@ def check(status: int) -> None:
 
 
 def make_opts(sum="fds", acc="dd", term_begin=0, term_end=-1, scaled=True, schedule=-1,
-              workspace=None, out_lo=None) -> LhOpts:
+              workspace=None, out_lo=None, saved=None) -> LhOpts:
     o = LhOpts()
     lib().lh_opts_default(ctypes.byref(o))
     o.sum = _SUMS[sum]
@@ -105,6 +109,9 @@ def make_opts(sum="fds", acc="dd", term_begin=0, term_end=-1, scaled=True, sched
         o.ws_bytes = workspace.numel() * workspace.element_size()
     if out_lo is not None:
         o.out_lo = ctypes.c_void_p(out_lo.data_ptr())
+    if saved is not None:
+        o.saved = ctypes.c_void_p(saved.data_ptr())
+        o.saved_count = saved.numel()
     return o
 
 

@@ -106,18 +106,40 @@ def lhaf_batched_workspace(idx_off, r=None, **kw) -> int:
                                                ctypes.byref(o)))
 
 
+def lhaf_saved_count(idx_off, r=None, sum="fds") -> int:
+    """Entries of the per-term coefficient store of a batch (complex128)."""
+    off = np.ascontiguousarray(idx_off, dtype=np.int64)
+    rr = None if r is None else np.ascontiguousarray(r, dtype=np.int32)
+    o = Bn.make_opts(sum)
+    v = int(Bn.lib().lhaf_saved_count(len(off) - 1, Bn.host_ptr(off), Bn.host_ptr(rr),
+                                      ctypes.byref(o)))
+    if v < 0:
+        Bn.check(-v)
+    return v
+
+
+def _saved_tensor(saved, device):
+    if saved is None:
+        return None
+    if saved.dtype != torch.complex128 or saved.device != device or not saved.is_contiguous():
+        raise ValueError("saved must be a contiguous complex128 tensor on the problems' device")
+    return saved
+
+
 def lhaf_batched(A, gamma, idx=None, idx_off=None, r=None, *, sum="fds", acc="dd",
                  term_begin=0, term_end=-1, scaled=True, schedule=-1, return_error=False,
-                 return_lo=False, workspace=None):
+                 return_lo=False, workspace=None, saved=None):
     """Many loop hafnians in one persistent launch.  Either a dense stack
     A (B,N,N), gamma (B,N), or a shared base A (M,M), gamma (M) with index
     lists idx[idx_off[b]:idx_off[b+1]] (r: optional multiplicities packed like
-    idx)."""
+    idx).  saved: optional complex128 tensor of lhaf_saved_count(...) entries
+    that receives the per-term coefficients for lhaf_backward."""
     A, gamma, Bsz, lda, sA, sg, off, idx_t, rr = _batch_args(A, gamma, idx, idx_off, r)
     out = torch.empty(Bsz, dtype=torch.complex128, device=A.device)
     err = torch.empty(Bsz, dtype=torch.float64, device=A.device)
     lo = torch.zeros(Bsz, dtype=torch.complex128, device=A.device) if return_lo else None
-    o = Bn.make_opts(sum, acc, term_begin, term_end, scaled, schedule, None, lo)
+    o = Bn.make_opts(sum, acc, term_begin, term_end, scaled, schedule, None, lo,
+                     _saved_tensor(saved, A.device))
     need = int(Bn.lib().lhaf_batched_workspace(Bsz, Bn.host_ptr(off), Bn.host_ptr(rr), ctypes.byref(o)))
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
@@ -135,9 +157,10 @@ def lhaf_batched(A, gamma, idx=None, idx_off=None, r=None, *, sum="fds", acc="dd
 
 
 def lhaf_backward(A, gamma, grad_out, idx=None, idx_off=None, r=None, *, sum="fds",
-                  acc="dd", schedule=-1, workspace=None):
+                  acc="dd", schedule=-1, workspace=None, saved=None):
     """Gradients (dA, dgamma) of the batch in PyTorch's complex convention:
-    grad_out * conj(d lhaf / d input)."""
+    grad_out * conj(d lhaf / d input).  saved: the coefficient store written
+    by lhaf_batched on the same batch and sum (skips the Hessenberg phase)."""
     A, gamma, Bsz, lda, sA, sg, off, idx_t, rr = _batch_args(A, gamma, idx, idx_off, r)
     grad_out = _dev_c128(grad_out, "grad_out").reshape(-1)
     if grad_out.numel() != Bsz:
@@ -145,7 +168,7 @@ def lhaf_backward(A, gamma, grad_out, idx=None, idx_off=None, r=None, *, sum="fd
     base_dim = A.shape[-1]
     dA = torch.empty_like(A)
     dg = torch.empty_like(gamma)
-    o = Bn.make_opts(sum, acc, 0, -1, True, schedule)
+    o = Bn.make_opts(sum, acc, 0, -1, True, schedule, saved=_saved_tensor(saved, A.device))
     need = int(Bn.lib().lhaf_backward_workspace(Bsz, Bn.host_ptr(off), Bn.host_ptr(rr), base_dim,
                                                 ctypes.byref(o)))
     if workspace is None or workspace.numel() < need:
@@ -158,28 +181,50 @@ def lhaf_backward(A, gamma, grad_out, idx=None, idx_off=None, r=None, *, sum="fd
     return dA, dg
 
 
+def _store_fits(count: int, device, fraction: float) -> bool:
+    """Whether a coefficient store of `count` entries fits in the given
+    fraction of the device's free memory."""
+    free, _ = torch.cuda.mem_get_info(device)
+    return count * 16 <= fraction * free
+
+
 class LhafFunction(torch.autograd.Function):
     """lhaf of a dense batch (A (B,N,N), gamma (B,N)) with the adjoint kernel
-    as backward."""
+    as backward.  When gradients are needed and the per-term coefficient
+    store fits in `store_fraction` of free device memory, the forward keeps it
+    and the backward skips the Hessenberg phase."""
 
     @staticmethod
-    def forward(ctx, A, gamma, sum="fds", acc="dd", r=None):
+    def forward(ctx, A, gamma, sum="fds", acc="dd", r=None, store_fraction=0.5):
+        saved = None
+        if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
+            off = np.arange(A.shape[0] + 1, dtype=np.int64) * A.shape[1]
+            rr = None if r is None else np.asarray(r, dtype=np.int32).reshape(-1)
+            count = lhaf_saved_count(off, rr, sum)
+            if count > 0 and _store_fits(count, A.device, store_fraction):
+                saved = torch.empty(count, dtype=torch.complex128, device=A.device)
         ctx.save_for_backward(A, gamma)
+        ctx.store = saved
         ctx.opts = (sum, acc, r)
-        out = lhaf_batched(A, gamma, r=r, sum=sum, acc=acc)
+        out = lhaf_batched(A, gamma, r=r, sum=sum, acc=acc, saved=saved)
         return out
 
     @staticmethod
     def backward(ctx, grad_out):
         A, gamma = ctx.saved_tensors
         sum, acc, r = ctx.opts
-        dA, dg = lhaf_backward(A, gamma, grad_out.contiguous(), r=r, sum=sum, acc=acc)
-        return dA, dg, None, None, None
+        # the store stays with the graph (a retained graph's second backward
+        # must give the same bits)
+        dA, dg = lhaf_backward(A, gamma, grad_out.contiguous(), r=r, sum=sum, acc=acc,
+                               saved=ctx.store)
+        return dA, dg, None, None, None, None
 
 
-def lhaf_autograd(A, gamma, sum="fds", acc="dd", r=None):
+def lhaf_autograd(A, gamma, sum="fds", acc="dd", r=None, store_fraction=0.5):
+    """Differentiable lhaf of one matrix (A (N,N)) or a dense batch (A (B,N,N));
+    store_fraction = 0 always recomputes the per-term coefficients."""
     squeeze = A.dim() == 2
     if squeeze:
         A, gamma = A.unsqueeze(0), gamma.unsqueeze(0)
-    out = LhafFunction.apply(A, gamma, sum, acc, r)
+    out = LhafFunction.apply(A, gamma, sum, acc, r, store_fraction)
     return out[0] if squeeze else out

@@ -160,6 +160,7 @@ struct Plan {
   size_t c_elems = 0;
   int bmax = 1, nmax = 0;
   int grid = 1;
+  int64_t saved_need = 0;  // entries of the per-term coefficient store
   Layout lay;
 };
 
@@ -205,6 +206,11 @@ lh_status build_plan(std::vector<ProblemIn>& pin, const lh_opts& o, int dev, Pla
     }
     P.c_off = (int64_t)pl.c_elems;
     pl.c_elems += (size_t)(8 * P.B) * (8 * P.B) + 64;
+    P.s_off = -1;
+    if (P.n > 0) {
+      P.s_off = pl.saved_need;
+      pl.saved_need += P.T * P.n;
+    }
     pl.aoff[b] = pin[b].a_off;
     pl.goff[b] = pin[b].g_off;
     pl.ioff[b] = pin[b].i_off;
@@ -325,14 +331,15 @@ using namespace lh;
 namespace lh {
 
 template <int BMAX>
-static hipError_t launch_fwd(const Plan& pl, char* base, int acc_dd, hipStream_t st) {
+static hipError_t launch_fwd(const Plan& pl, char* base, int acc_dd, cd* saved, hipStream_t st) {
   const size_t lds = lds_bytes_for(std::max(pl.nmax, 1));
   hipLaunchKernelGGL(HIP_KERNEL_NAME(forward_kernel<BMAX>), dim3(pl.grid), dim3(64), lds, st,
                      reinterpret_cast<const Prob*>(base + pl.lay.probs),
                      reinterpret_cast<const Item*>(base + pl.lay.items), (int)pl.items.size(),
                      reinterpret_cast<int*>(base + pl.lay.counter),
                      reinterpret_cast<const cd*>(base + pl.lay.cdata),
-                     reinterpret_cast<Partial*>(base + pl.lay.parts), acc_dd, std::max(pl.nmax, 1));
+                     reinterpret_cast<Partial*>(base + pl.lay.parts), acc_dd, std::max(pl.nmax, 1),
+                     saved);
   return hipGetLastError();
 }
 
@@ -358,17 +365,18 @@ lh_status run_forward(Plan& pl, const lh_c128* A, int64_t lda, const lh_c128* g,
                      reinterpret_cast<int*>(base + pl.lay.counter));
   if (hipGetLastError() != hipSuccess) return LH_EHIP;
   const int acc_dd = o.acc == LH_ACC_DD ? 1 : 0;
+  cd* sv = reinterpret_cast<cd*>(o.saved);
   if (!pl.items.empty()) {
     hipError_t e;
     switch (pl.bmax) {
-      case 1: e = launch_fwd<1>(pl, base, acc_dd, st); break;
-      case 2: e = launch_fwd<2>(pl, base, acc_dd, st); break;
-      case 3: e = launch_fwd<3>(pl, base, acc_dd, st); break;
-      case 4: e = launch_fwd<4>(pl, base, acc_dd, st); break;
-      case 5: e = launch_fwd<5>(pl, base, acc_dd, st); break;
-      case 6: e = launch_fwd<6>(pl, base, acc_dd, st); break;
-      case 7: e = launch_fwd<7>(pl, base, acc_dd, st); break;
-      default: e = launch_fwd<8>(pl, base, acc_dd, st); break;
+      case 1: e = launch_fwd<1>(pl, base, acc_dd, sv, st); break;
+      case 2: e = launch_fwd<2>(pl, base, acc_dd, sv, st); break;
+      case 3: e = launch_fwd<3>(pl, base, acc_dd, sv, st); break;
+      case 4: e = launch_fwd<4>(pl, base, acc_dd, sv, st); break;
+      case 5: e = launch_fwd<5>(pl, base, acc_dd, sv, st); break;
+      case 6: e = launch_fwd<6>(pl, base, acc_dd, sv, st); break;
+      case 7: e = launch_fwd<7>(pl, base, acc_dd, sv, st); break;
+      default: e = launch_fwd<8>(pl, base, acc_dd, sv, st); break;
     }
     if (e != hipSuccess) return LH_EHIP;
   }
@@ -447,22 +455,12 @@ int32_t lhaf_plan_pairs(int32_t N, const int32_t* r, int32_t* pos, int32_t* eta)
   return pp.H;
 }
 
-static lh_status validate_opts(const lh_opts* opts, lh_opts& o) {
-  lh_opts_default(&o);
-  if (opts) o = *opts;
-  if (o.sum != LH_SUM_ET && o.sum != LH_SUM_FDS) return LH_EINVAL;
-  if (o.acc != LH_ACC_FP64 && o.acc != LH_ACC_DD) return LH_EINVAL;
-  return LH_OK;
-}
-
-static lh_status batched_impl(int32_t B, const lh_c128* A_base, int64_t lda, int64_t stride_A,
-                              const lh_c128* gamma_base, int64_t stride_g, const int32_t* idx,
-                              const int64_t* idx_off, const int32_t* r, lh_c128* out,
-                              double* err_est, void* workspace, size_t ws_bytes,
-                              const lh_opts& o, hipStream_t st, bool query_only,
-                              size_t* need_bytes) {
+// Pair plans of the problems of a batch (index lists idx_off, optional
+// multiplicities r packed like the index lists).
+static lh_status parse_problems(int32_t B, const int64_t* idx_off, const int32_t* r,
+                                int64_t stride_A, int64_t stride_g, std::vector<ProblemIn>& pin) {
   if (B < 0 || !idx_off) return LH_EINVAL;
-  std::vector<ProblemIn> pin(B);
+  pin.assign(B, ProblemIn());
   for (int b = 0; b < B; ++b) {
     const int64_t s0 = idx_off[b], s1 = idx_off[b + 1];
     if (s1 < s0 || s0 < 0) return LH_EINVAL;
@@ -483,6 +481,27 @@ static lh_status batched_impl(int32_t B, const lh_c128* A_base, int64_t lda, int
     pin[b].g_off = (int64_t)b * stride_g;
     pin[b].i_off = s0;
   }
+  return LH_OK;
+}
+
+static lh_status validate_opts(const lh_opts* opts, lh_opts& o) {
+  lh_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.sum != LH_SUM_ET && o.sum != LH_SUM_FDS) return LH_EINVAL;
+  if (o.acc != LH_ACC_FP64 && o.acc != LH_ACC_DD) return LH_EINVAL;
+  if (o.saved && o.saved_count < 0) return LH_EINVAL;
+  return LH_OK;
+}
+
+static lh_status batched_impl(int32_t B, const lh_c128* A_base, int64_t lda, int64_t stride_A,
+                              const lh_c128* gamma_base, int64_t stride_g, const int32_t* idx,
+                              const int64_t* idx_off, const int32_t* r, lh_c128* out,
+                              double* err_est, void* workspace, size_t ws_bytes,
+                              const lh_opts& o, hipStream_t st, bool query_only,
+                              size_t* need_bytes) {
+  std::vector<ProblemIn> pin;
+  lh_status ps = parse_problems(B, idx_off, r, stride_A, stride_g, pin);
+  if (ps != LH_OK) return ps;
   int dev = 0;
   if (!query_only || true) {
     lh_status s = ensure_device(dev);
@@ -494,6 +513,10 @@ static lh_status batched_impl(int32_t B, const lh_c128* A_base, int64_t lda, int
   if (query_only) {
     *need_bytes = pl.lay.total;
     return LH_OK;
+  }
+  if (o.saved) {
+    if (o.term_begin != 0 || o.term_end != -1) return LH_EUNSUPPORTED;
+    if (o.saved_count < pl.saved_need) return LH_ENOMEM;
   }
   if (B == 0) return LH_OK;
   if (!A_base || !gamma_base || !out || lda < 1) return LH_EINVAL;
@@ -588,28 +611,9 @@ static lh_status backward_impl(int32_t B, const lh_c128* A_base, int64_t lda, in
                                lh_c128* dA, lh_c128* dgamma, int32_t base_dim, void* workspace,
                                size_t ws_bytes, const lh_opts& o, hipStream_t st, bool query_only,
                                size_t* need_bytes) {
-  if (B < 0 || !idx_off) return LH_EINVAL;
-  std::vector<ProblemIn> pin(B);
-  for (int b = 0; b < B; ++b) {
-    const int64_t s0 = idx_off[b], s1 = idx_off[b + 1];
-    if (s1 < s0 || s0 < 0) return LH_EINVAL;
-    const int64_t N = s1 - s0;
-    if (r) {
-      int64_t tot = 0;
-      for (int64_t k = s0; k < s1; ++k) {
-        if (r[k] < 0) return LH_EINVAL;
-        tot += r[k];
-      }
-      if (N > kMaxRows || tot > kMaxN) return LH_ESIZE;
-      pin[b].plan = plan_repeated(r + s0, (int)N);
-    } else {
-      if (N > kMaxN) return LH_ESIZE;
-      pin[b].plan = plan_plain((int)N);
-    }
-    pin[b].a_off = (int64_t)b * stride_A;
-    pin[b].g_off = (int64_t)b * stride_g;
-    pin[b].i_off = s0;
-  }
+  std::vector<ProblemIn> pin;
+  lh_status ps = parse_problems(B, idx_off, r, stride_A, stride_g, pin);
+  if (ps != LH_OK) return ps;
   int dev = 0;
   lh_status s = ensure_device(dev);
   if (s != LH_OK) return s;
@@ -639,6 +643,7 @@ static lh_status backward_impl(int32_t B, const lh_c128* A_base, int64_t lda, in
   if (stride_A == 0 && base_dim < 1) return LH_EINVAL;
   if (!workspace) return LH_EINVAL;
   if (ws_bytes < total) return LH_ENOMEM;
+  if (o.saved && o.saved_count < pl.saved_need) return LH_ENOMEM;
   char* base = static_cast<char*>(workspace);
   s = upload_plan(pl, base, st, dev);
   if (s != LH_OK) return s;
@@ -661,7 +666,7 @@ static lh_status backward_impl(int32_t B, const lh_c128* A_base, int64_t lda, in
                      reinterpret_cast<const Item*>(base + pl.lay.items), (int)pl.items.size(),  \
                      reinterpret_cast<int*>(base + pl.lay.counter),                             \
                      reinterpret_cast<const cd*>(base + pl.lay.cdata), gsl, scratch,            \
-                     std::max(pl.nmax, 1))
+                     std::max(pl.nmax, 1), reinterpret_cast<const cd*>(o.saved))
     switch (pl.bmax) {
       case 1: LH_BLAUNCH(1); break;
       case 2: LH_BLAUNCH(2); break;
@@ -691,6 +696,20 @@ static lh_status backward_impl(int32_t B, const lh_c128* A_base, int64_t lda, in
   }
   if (hipGetLastError() != hipSuccess) return LH_EHIP;
   return LH_OK;
+}
+
+int64_t lhaf_saved_count(int32_t B, const int64_t* idx_off, const int32_t* r, const lh_opts* opts) {
+  lh_opts o;
+  lh_status s = validate_opts(opts, o);
+  if (s != LH_OK) return -s;
+  std::vector<ProblemIn> pin;
+  s = parse_problems(B, idx_off, r, 0, 0, pin);
+  if (s != LH_OK) return -s;
+  int64_t tot = 0;
+  for (auto& pi : pin) {
+    if (pi.plan.n > 0) tot += term_count(pi.plan, o.sum == LH_SUM_FDS ? 1 : 0, nullptr) * pi.plan.n;
+  }
+  return tot;
 }
 
 size_t lhaf_backward_workspace(int32_t B, const int64_t* idx_off, const int32_t* r,

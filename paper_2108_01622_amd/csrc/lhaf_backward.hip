@@ -133,7 +133,7 @@ __device__ __forceinline__ void krylov_b(const double (&Wr)[B][B], const double 
                                          const double dlane, const cd* __restrict__ vp,
                                          const int m, const int H, const int n, const int p,
                                          const int q, const int lane, cd* __restrict__ bv,
-                                         LdsView& L) {
+                                         LdsView& L, const bool with_mu) {
   if (lane < 8 * B) bv[lane] = vp[lane];
   __syncthreads();
   for (int j = 0; j + 1 < n; ++j) {
@@ -150,6 +150,7 @@ __device__ __forceinline__ void krylov_b(const double (&Wr)[B][B], const double 
     }
     __syncthreads();
   }
+  if (!with_mu) return;
   // mu_k = sum_c u_c b_{k-1}[c], u_c = d_{pair(c)} v_{partner(c)}
   const int pl = lane < H ? lane + H : lane - H;
   const cd ul = lane < m ? cscale(dlane, vp[pl & 63]) : czero();
@@ -225,12 +226,14 @@ __device__ __forceinline__ void accumulate_g(cd* __restrict__ G, const double co
 
 // Gradient of the terms [t0, t1) of problem P into the item slot
 // G[LD*LD] (accumulated as sum_t c_t d_{pair(j)} M_t[j][c], M = (d f/d W)^T)
-// and G[LD*LD + l] (d f / d v_l).
+// and G[LD*LD + l] (d f / d v_l).  With a coefficient store written by the
+// forward pass, the a_k are read instead of recomputed.
 template <int B, bool kStage>
 __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, const int64_t t1,
                                              const cd* __restrict__ Cp,
                                              const cd* __restrict__ vp, cd* __restrict__ G,
-                                             cd* __restrict__ scr, LdsView& L) {
+                                             cd* __restrict__ scr, LdsView& L,
+                                             const cd* __restrict__ saved) {
   constexpr int LD = 8 * B;
   constexpr int S = kStage ? LD : 64;    // stride of the Krylov vectors
   const int lane = threadIdx.x & 63;
@@ -275,16 +278,16 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
     const double dsh = shfl_d(wl, lpair & 63);
     const double dlane = lane < m ? dsh : 0.0;
 
+    cd asaved = czero();
+    if (saved && lane >= 1 && lane <= n) asaved = saved[P.s_off + t * n + (lane - 1)];
     double Wr[B][B], Wi[B][B];
     load_w<B>(Cp, dcol, p, q, Wr, Wi);
-    krylov_b<B, S>(Wr, Wi, dlane, vp, m, H, n, p, q, lane, bv, L);
-    spectral_series<B>(Wr, Wi, m, n, p, q, lane, L);
-    // e_j = sum_k q_k L_{j-k};  a_k = e_{n-k} / 2 (k = 1..n)
-    if (lane >= 1 && lane <= n) {
-      const int j = n - lane;
-      cd e = czero();
-      for (int k = 0; k <= j; ++k) e = cfma(L.ser[k], L.ser[33 + j - k], e);
-      acoef[lane] = cscale(0.5, e);
+    krylov_b<B, S>(Wr, Wi, dlane, vp, m, H, n, p, q, lane, bv, L, saved == nullptr);
+    if (saved) {
+      if (lane >= 1 && lane <= n) acoef[lane] = asaved;
+    } else {
+      spectral_series<B>(Wr, Wi, m, n, p, q, lane, L);
+      if (lane >= 1 && lane <= n) acoef[lane] = series_coef(L, n, lane);
     }
     __syncthreads();
 
@@ -393,7 +396,8 @@ __global__ LH_BWD_ATTR void backward_kernel(const Prob* __restrict__ probs,
                                                       const Item* __restrict__ items, int n_items,
                                                       int* counter, const cd* __restrict__ ws,
                                                       cd* __restrict__ gslots,
-                                                      cd* __restrict__ scratch, int nmax) {
+                                                      cd* __restrict__ scratch, int nmax,
+                                                      const cd* __restrict__ saved) {
   extern __shared__ __align__(16) char lds_raw[];
   LdsView L = carve(lds_raw, nmax);
   const int lane = threadIdx.x & 63;
@@ -410,7 +414,7 @@ __global__ LH_BWD_ATTR void backward_kernel(const Prob* __restrict__ probs,
     switch (P.B) {
 #define LH_BCASE(BB)                                                                   \
   case BB:                                                                             \
-    if (BB <= BMAX) run_item_bwd<(BB <= BMAX ? BB : 1), (BMAX <= kStageMaxB)>(P, I.t0, I.t1, Cp, vp, G, scr, L); \
+    if (BB <= BMAX) run_item_bwd<(BB <= BMAX ? BB : 1), (BMAX <= kStageMaxB)>(P, I.t0, I.t1, Cp, vp, G, scr, L, saved); \
     break;
       LH_BCASE(1)
       LH_BCASE(2)

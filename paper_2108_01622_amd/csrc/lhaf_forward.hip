@@ -421,12 +421,29 @@ __device__ __forceinline__ void spectral_series(double (&Wr)[B][B], double (&Wi)
   }
 }
 
+// Lane k (1 <= k <= n): a_k = e_{n-k} / 2, where e_j = sum_{i<=j} q_i L_{j-i}
+// is the lambda^j coefficient of f(lambda) (the weights of the power sums in
+// the adjoint: d f / d g_k = e_{n-k}).
+__device__ __forceinline__ cd series_coef(const LdsView& L, const int n, const int lane) {
+  const int j = n - lane;
+  cd e0 = czero(), e1 = czero();
+  int i = 0;
+  for (; i + 1 <= j; i += 2) {
+    e0 = cfma(L.ser[i], L.ser[33 + j - i], e0);
+    e1 = cfma(L.ser[i + 1], L.ser[33 + j - i - 1], e1);
+  }
+  if (i <= j) e0 = cfma(L.ser[i], L.ser[33 + j - i], e0);
+  return cscale(0.5, cadd(e0, e1));
+}
+
 // -------------------------------------------------------------------------
-// Evaluate terms [t0, t1) of problem P; writes the item's partial sum.
+// Evaluate terms [t0, t1) of problem P; writes the item's partial sum (and,
+// with a coefficient store, the a_k of every term).
 template <int B>
 __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const int64_t t1,
                                          const cd* __restrict__ Cp, const cd* __restrict__ vp,
-                                         Partial* __restrict__ out, LdsView& L, const int acc_dd) {
+                                         Partial* __restrict__ out, LdsView& L, const int acc_dd,
+                                         cd* __restrict__ saved) {
   const int lane = threadIdx.x & 63;
   const int p = lane >> 3, q = lane & 7;
   const int m = P.m, H = P.H, n = P.n;
@@ -461,6 +478,7 @@ __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const 
       acci.hi = fma(coef, f.i, acci.hi);
     }
     sabs = fma(fabs(coef), sqrt(cabs2(f)), sabs);
+    if (saved && lane >= 1 && lane <= n) saved[P.s_off + t * n + (lane - 1)] = series_coef(L, n, lane);
     __syncthreads();
   }
   if (lane == 0) {
@@ -540,7 +558,7 @@ __attribute__((amdgpu_waves_per_eu(LH_FWD_WAVES(BMAX), LH_FWD_WAVES(BMAX)))) voi
                                                      const Item* __restrict__ items, int n_items,
                                                      int* counter, const cd* __restrict__ ws,
                                                      Partial* __restrict__ parts, int acc_dd,
-                                                     int nmax) {
+                                                     int nmax, cd* __restrict__ saved) {
   extern __shared__ __align__(16) char lds_raw[];
   LdsView L = carve(lds_raw, nmax);
   const int lane = threadIdx.x & 63;
@@ -559,7 +577,7 @@ __attribute__((amdgpu_waves_per_eu(LH_FWD_WAVES(BMAX), LH_FWD_WAVES(BMAX)))) voi
     switch (P.B) {
 #define LH_CASE(BB)                                                     \
   case BB:                                                              \
-    if (BB <= BMAX) run_item<(BB <= BMAX ? BB : 1)>(P, I.t0, I.t1, Cp, vp, parts + I.pad, L, acc_dd); \
+    if (BB <= BMAX) run_item<(BB <= BMAX ? BB : 1)>(P, I.t0, I.t1, Cp, vp, parts + I.pad, L, acc_dd, saved); \
     break;
       LH_CASE(1)
       LH_CASE(2)

@@ -86,3 +86,22 @@ def test_invalid_arguments(L):
                                    ctypes.c_void_p(np.zeros(200, np.int32).ctypes.data)) == -2
     r = np.array([1, -1], dtype=np.int32)
     assert L.lib().lhaf_term_count(2, L.host_ptr(r), 1) == -1
+
+
+def test_saved_count(L):
+    """Entries of the per-term coefficient store: sum over problems of terms x n."""
+    import ctypes
+    lib = L.lib()
+    for s in ("fds", "et"):
+        o = L.make_opts(sum=s)
+        off = np.array([0, 40, 80, 91], dtype=np.int64)  # N = 40, 40, 11 (padded to 12)
+        want = 2 * L.term_count(40, sum=s) * 20 + L.term_count(11, sum=s) * 6
+        assert lib.lhaf_saved_count(3, L.host_ptr(off), None, ctypes.byref(o)) == want
+        r = np.array([2, 1, 3, 0, 1], dtype=np.int32)  # one repeated problem, n = 7/2 -> 4
+        off = np.array([0, 5], dtype=np.int64)
+        assert lib.lhaf_saved_count(1, L.host_ptr(off), L.host_ptr(r), ctypes.byref(o)) == \
+            L.term_count(5, r, sum=s) * 4
+        off = np.array([0, 0], dtype=np.int64)  # empty problem: no terms stored
+        assert lib.lhaf_saved_count(1, L.host_ptr(off), None, ctypes.byref(o)) == 0
+    bad = np.array([0, 65], dtype=np.int64)
+    assert lib.lhaf_saved_count(1, L.host_ptr(bad), None, ctypes.byref(L.make_opts())) == -2

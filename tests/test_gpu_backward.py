@@ -186,3 +186,78 @@ def test_autograd_gradcheck(T, api):
     gt = dev(T, g).requires_grad_(True)
     assert T.autograd.gradcheck(lambda a, b: api.lhaf_autograd(a, b), (At, gt), eps=1e-6, atol=1e-7,
                                 rtol=1e-5, fast_mode=False)
+
+
+def _saved_vs_recomputed(T, api, A, g, idx=None, idx_off=None, r=None, mode="fds", go=None):
+    At, gt = dev(T, A), dev(T, g)
+    off = idx_off if idx_off is not None else np.arange(A.shape[0] + 1, dtype=np.int64) * A.shape[1]
+    count = api.lhaf_saved_count(off, r, sum=mode)
+    store = T.empty(count, dtype=T.complex128, device="cuda")
+    nb = len(off) - 1
+    gout = dev(T, go if go is not None else np.ones(nb))
+    out_s = api.lhaf_batched(At, gt, idx=idx, idx_off=idx_off, r=r, sum=mode, saved=store)
+    out = api.lhaf_batched(At, gt, idx=idx, idx_off=idx_off, r=r, sum=mode)
+    assert T.equal(out_s, out)  # saving does not change the forward result
+    dA_s, dg_s = api.lhaf_backward(At, gt, gout, idx=idx, idx_off=idx_off, r=r, sum=mode, saved=store)
+    dA, dg = api.lhaf_backward(At, gt, gout, idx=idx, idx_off=idx_off, r=r, sum=mode)
+    # both paths are correct to rounding; the ET sum cancels more than FDS
+    tol = 1e-12 if mode == "fds" else 1e-10
+    scale_A = max(float(dA.abs().max()), 1e-300)
+    scale_g = max(float(dg.abs().max()), 1e-300)
+    assert float((dA_s - dA).abs().max()) / scale_A < tol
+    assert float((dg_s - dg).abs().max()) / scale_g < tol
+
+
+@pytest.mark.parametrize("mode", ["fds", "et"])
+def test_saved_store_dense(T, api, mode):
+    """Backward from the forward's coefficient store equals the backward that
+    recomputes the Hessenberg phase (N = 24, 25 and 7 in one dense batch of
+    the largest size is not possible, so three batches)."""
+    rng = np.random.Generator(np.random.PCG64(4242))
+    for N, cnt in ((24, 3), (25, 2), (7, 4)):
+        mats = [I.gaussian_state_matrix(N, rng) for _ in range(cnt)]
+        A = np.stack([m[0] for m in mats])
+        g = np.stack([m[1] for m in mats])
+        _saved_vs_recomputed(T, api, A, g, mode=mode, go=np.linspace(1, 2, cnt) - 0.5j)
+
+
+def test_saved_store_shared_and_repeated(T, api):
+    base = I.state100(0)
+    Bm, gam = base["B"], base["gamma"]
+    idx = np.concatenate([np.arange(0, 30, 2), np.arange(5, 41), np.array([3, 10, 99])])
+    off = np.array([0, 15, 51, 54], dtype=np.int64)
+    _saved_vs_recomputed(T, api, Bm, gam, idx=idx, idx_off=off)
+    r = np.array([2, 1, 3, 0, 1, 2, 1], dtype=np.int32)
+    A, g = I.random_symmetric(7, 777)
+    _saved_vs_recomputed(T, api, A[None], g[None], r=r)
+
+
+def test_saved_store_errors(T, api):
+    from paper_2108_01622_amd._binding import LhafError
+    A, g = I.random_symmetric(12, 1212)
+    At, gt = dev(T, A)[None], dev(T, g)[None]
+    count = api.lhaf_saved_count(np.array([0, 12]))
+    small = T.empty(count - 1, dtype=T.complex128, device="cuda")
+    with pytest.raises(LhafError, match="workspace too small"):
+        api.lhaf_batched(At, gt, saved=small)
+    full = T.empty(count, dtype=T.complex128, device="cuda")
+    with pytest.raises(LhafError, match="unsupported"):
+        api.lhaf_batched(At, gt, saved=full, term_begin=0, term_end=5, scaled=False)
+    with pytest.raises(LhafError, match="workspace too small"):
+        api.lhaf_backward(At, gt, T.ones(1, dtype=T.complex128, device="cuda"), saved=small)
+
+
+def test_autograd_with_and_without_store(T, api):
+    rng = np.random.Generator(np.random.PCG64(31))
+    mats = [I.gaussian_state_matrix(16, rng) for _ in range(3)]
+    A = np.stack([m[0] for m in mats])
+    g = np.stack([m[1] for m in mats])
+    res = []
+    for frac in (0.5, 0.0):
+        At = dev(T, A).requires_grad_(True)
+        gt = dev(T, g).requires_grad_(True)
+        out = api.lhaf_autograd(At, gt, store_fraction=frac)
+        (out * dev(T, np.array([1.0, -1j, 0.5]))).sum().real.backward()
+        res.append((At.grad.clone(), gt.grad.clone()))
+    for a, b in zip(res[0], res[1]):
+        assert float((a - b).abs().max()) <= 1e-12 * float(b.abs().max())
