@@ -53,6 +53,14 @@ __host__ __device__ inline size_t bwd_x_elems(int bmax, int nmax) {
 inline size_t bwd_lds_bytes(int bmax, int nmax) {
   return lds_bytes_for(nmax) + sizeof(cd) * bwd_x_elems(bmax, nmax);
 }
+// Lanes of the wavefront exchange data through LDS only when staging (and
+// through the global scratch otherwise, which needs the full barrier).
+template <bool kLds>
+__device__ __forceinline__ void lane_sync() {
+  if constexpr (kLds) wave_sync();
+  else __syncthreads();
+}
+
 // X starts after the forward layout (16-byte aligned)
 __device__ __forceinline__ cd* lds_x(const LdsView& L) { return L.ring + L.NP * L.NR; }
 
@@ -128,14 +136,14 @@ __device__ __forceinline__ void store_mat(const double (&Rr)[B][B], const double
 // alpha_i = (W^T)^i u needs no products: X_d W is symmetric, so
 // (W^T)^i X_d = X_d W^i and alpha_i = X_d b_i, i.e.
 // alpha_i[c] = d_{pair(c)} b_i[partner(c)].
-template <int B, int S>
+template <int B, int S, bool kLds>
 __device__ __forceinline__ void krylov_b(const double (&Wr)[B][B], const double (&Wi)[B][B],
                                          const double dlane, const cd* __restrict__ vp,
                                          const int m, const int H, const int n, const int p,
                                          const int q, const int lane, cd* __restrict__ bv,
                                          LdsView& L, const bool with_mu) {
   if (lane < 8 * B) bv[lane] = vp[lane];
-  __syncthreads();
+  lane_sync<kLds>();
   for (int j = 0; j + 1 < n; ++j) {
     cd xc[B];
 #pragma unroll
@@ -148,7 +156,7 @@ __device__ __forceinline__ void krylov_b(const double (&Wr)[B][B], const double 
       y = sum_row8(y);
       if (q == 0) bv[S * (j + 1) + 8 * a + p] = y;
     }
-    __syncthreads();
+    lane_sync<kLds>();
   }
   if (!with_mu) return;
   // mu_k = sum_c u_c b_{k-1}[c], u_c = d_{pair(c)} v_{partner(c)}
@@ -160,7 +168,7 @@ __device__ __forceinline__ void krylov_b(const double (&Wr)[B][B], const double 
     const double im = sum_col8(sum_row8(t.i));
     if (lane == 0) L.mu[k] = mk(re, im);
   }
-  __syncthreads();
+  lane_sync<kLds>();
 }
 
 // R += sum_{i+j <= n-2} a_{i+j+2} b_j alpha_i^T = sum_i beta_i alpha_i^T with
@@ -184,7 +192,7 @@ __device__ __forceinline__ void rank_terms(double (&Rr)[B][B], double (&Ri)[B][B
     }
     cd* bb = xb + 64 * (i & 1);
     bb[lane] = cadd(b0, b1);
-    __syncthreads();
+    wave_sync();
     cd beta[B], al[B];
 #pragma unroll
     for (int a = 0; a < B; ++a) beta[a] = bb[8 * a + p];
@@ -262,7 +270,7 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
     bool empty;
     const double wl = term_weight(it, P, lane, coef, empty);
     if (empty) {
-      __syncthreads();
+      lane_sync<kStage>();
       continue;
     }
     double dcol[B], drow[B];
@@ -282,14 +290,14 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
     if (saved && lane >= 1 && lane <= n) asaved = saved[P.s_off + t * n + (lane - 1)];
     double Wr[B][B], Wi[B][B];
     load_w<B>(Cp, dcol, p, q, Wr, Wi);
-    krylov_b<B, S>(Wr, Wi, dlane, vp, m, H, n, p, q, lane, bv, L, saved == nullptr);
+    krylov_b<B, S, kStage>(Wr, Wi, dlane, vp, m, H, n, p, q, lane, bv, L, saved == nullptr);
     if (saved) {
       if (lane >= 1 && lane <= n) acoef[lane] = asaved;
     } else {
       spectral_series<B>(Wr, Wi, m, n, p, q, lane, L);
       if (lane >= 1 && lane <= n) acoef[lane] = series_coef(L, n, lane);
     }
-    __syncthreads();
+    lane_sync<kStage>();
 
     double Rr[B][B], Ri[B][B];
     // ---- rank-one terms sum_i beta_i alpha_i^T (while the Krylov vectors
@@ -313,7 +321,7 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
       if (k <= n) g0 = cfma(acoef[k], bv[S * (k - 1) + pl], g0);
       G[LD * LD + lane] = cfma(mk(2.0 * coef * dlane, 0.0), cadd(g0, g1), G[LD * LD + lane]);
     }
-    __syncthreads();
+    lane_sync<kStage>();
 
     // ---- P(W) = sum_{k=1..n} a_k W^{k-1} by Paterson-Stockmeyer.  W is
     // re-read from L2 (the pointer is hidden from the optimiser so it does
@@ -322,14 +330,14 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
     load_w<B>(Cp2, dcol, p, q, Wr, Wi);
     if (kStage) store_mat<B>(Wr, Wi, X, p, q);
     if (s > 1) store_mat<B>(Wr, Wi, pw, p, q);  // W^1
-    __syncthreads();
+    lane_sync<kStage>();
     const cd* Wop = kStage ? X : pw;
     cd* Yop = kStage ? X : pw + (s - 1) * LD * LD;
     for (int e = 2; e <= s; ++e) {
       mul_right<B>(Wr, Wi, Wop, p, q);  // W^e = W^{e-1} W
-      if (e == s) __syncthreads();      // every read of W precedes its overwrite
+      if (e == s) lane_sync<kStage>();  // every read of W precedes its overwrite
       store_mat<B>(Wr, Wi, e < s ? pw + (e - 1) * LD * LD : Yop, p, q);
-      __syncthreads();
+      lane_sync<kStage>();
     }
     // R = B_Q, then R <- R W^s + B_q for q = Q-1 .. 0, where
     // B_q = sum_{r=0..s-1} a_{qs+r+1} W^r
@@ -379,7 +387,7 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
       }
     }
     accumulate_g<B>(G, coef, drow, Rr, Ri, p, q);
-    __syncthreads();
+    lane_sync<kStage>();
   }
 }
 

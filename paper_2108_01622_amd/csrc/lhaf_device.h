@@ -115,6 +115,17 @@ __device__ __forceinline__ double prod_wave(double x) {
   return x;
 }
 
+// Synchronisation of the lanes of one wavefront for kernels that run one
+// wavefront per workgroup and exchange data between lanes only through LDS:
+// a wavefront's LDS operations execute in issue order, so it suffices that
+// the compiler keeps memory accesses on their side of this point.  Unlike
+// __syncthreads() it does not wait for outstanding global loads and stores.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------------------
 // double-double accumulation (Knuth TwoSum, FMA TwoProd)
 struct dd {

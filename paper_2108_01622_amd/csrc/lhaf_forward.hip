@@ -102,7 +102,7 @@ __device__ __forceinline__ void householder_step(double (&Wr)[B][B], double (&Wi
       L.wv[i] = x;
     }
   }
-  __syncthreads();
+  wave_sync();
   const double tau = L.sc[0];
   // ---- left: W <- W - w (tau w^* W), rows >= 8kb, columns >= 8kb
   {
@@ -185,7 +185,7 @@ __device__ __forceinline__ void charpoly_step(const double (&Wr)[B][B], const do
     for (int a = 0; a < B; ++a) L.col[8 * a + p] = mk(Wr[a][kb], Wi[a][kb]);
   }
   if (lane == 0) L.col[64] = czero();
-  __syncthreads();
+  wave_sync();
   const cd hJJ = L.col[J];
   const cd hnext = L.col[J + 1];
   if (J >= 1) {
@@ -193,7 +193,7 @@ __device__ __forceinline__ void charpoly_step(const double (&Wr)[B][B], const do
     else if (lane == J - 1) pi = hsub;
   }
   if (lane < J) L.wb[lane] = cmul(L.col[lane], pi);
-  __syncthreads();
+  wave_sync();
   const int t = (lane & 31) + 1;
   const int slot = lane >> 5;
   cd acc = czero(), acc2 = czero();
@@ -217,10 +217,10 @@ __device__ __forceinline__ void charpoly_step(const double (&Wr)[B][B], const do
   cd* Tcur = L.ring + ring_slot(J, L.NR) * L.NP;
   cd val = czero();
   if (slot == 0 && t <= n) val = csub(cfnma(hJJ, Tprev[t - 1], Tprev[t]), acc);
-  __syncthreads();
+  wave_sync();
   if (slot == 0 && t <= n) Tcur[t] = val;
   if (lane == 32) Tcur[0] = mk(1.0, 0.0);
-  __syncthreads();
+  wave_sync();
   hsub = hnext;
 }
 
@@ -342,7 +342,7 @@ __device__ __forceinline__ void loop_moments(const double (&Wr)[B][B], const dou
 #pragma unroll
   for (int k = 0; k < B; ++k) xc[k] = vp[8 * k + q];
   L.xb[lane] = vp[lane];
-  __syncthreads();
+  wave_sync();
   int cur = 0;
   for (int i = 0; 2 * i + 1 <= n; ++i) {
     const cd* xcur = L.xb + 64 * cur;
@@ -355,7 +355,7 @@ __device__ __forceinline__ void loop_moments(const double (&Wr)[B][B], const dou
     }
     part = sum_row8(part);
     if (lane == 0) L.mu[2 * i + 1] = part;
-    __syncthreads();
+    wave_sync();
     if (2 * i + 2 <= n) {
       cd* xnext = L.xb + 64 * (cur ^ 1);
       cd y[B];
@@ -370,7 +370,7 @@ __device__ __forceinline__ void loop_moments(const double (&Wr)[B][B], const dou
 #pragma unroll
         for (int a = 0; a < B; ++a) xnext[8 * a + p] = y[a];
       }
-      __syncthreads();
+      wave_sync();
       cd part2 = czero();
 #pragma unroll
       for (int k = 0; k < B; ++k) {
@@ -383,7 +383,7 @@ __device__ __forceinline__ void loop_moments(const double (&Wr)[B][B], const dou
 #pragma unroll
       for (int k = 0; k < B; ++k) xc[k] = xnext[8 * k + q];
       cur ^= 1;
-      __syncthreads();
+      wave_sync();
     }
   }
 }
@@ -398,7 +398,7 @@ __device__ __forceinline__ void spectral_series(double (&Wr)[B][B], double (&Wi)
                                                 const int m, const int n, const int p,
                                                 const int q, const int lane, LdsView& L) {
   if (lane <= n) L.ring[lane] = lane == 0 ? mk(1.0, 0.0) : czero();  // T_{-1} in slot 0
-  __syncthreads();
+  wave_sync();
   cd pi = czero(), hsub = czero();
   HessLoop<B, 0>::run(Wr, Wi, m, n, p, q, lane, pi, hsub, L);
   // Both series at once: lanes 0..31 build q, lanes 32..63 build L.  Step k
@@ -411,13 +411,13 @@ __device__ __forceinline__ void spectral_series(double (&Wr)[B][B], double (&Wi)
   const cd xj = j <= n ? xs[j] : czero();
   const double al = h == 0 ? -1.0 : 0.0;
   if ((lane & 31) == 0) ys[0] = mk(1.0, 0.0);
-  __syncthreads();
+  wave_sync();
   for (int k = 1; k <= n; ++k) {
     cd t = czero();
     if (j <= k) t = cmul(cscale(fma(al, (double)k, 0.5 * j), xj), ys[k - j]);
     t = sum_half32(t);
     if ((lane & 31) == 0) ys[k] = cscale(1.0 / k, t);
-    __syncthreads();
+    wave_sync();
   }
 }
 
@@ -457,7 +457,7 @@ __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const 
     bool empty;
     const double wl = term_weight(it, P, lane, coef, empty);
     if (empty) {
-      __syncthreads();
+      wave_sync();
       continue;
     }
     double dcol[B];
@@ -479,7 +479,7 @@ __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const 
     }
     sabs = fma(fabs(coef), sqrt(cabs2(f)), sabs);
     if (saved && lane >= 1 && lane <= n) saved[P.s_off + t * n + (lane - 1)] = series_coef(L, n, lane);
-    __syncthreads();
+    wave_sync();
   }
   if (lane == 0) {
     Partial pr;
