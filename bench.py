@@ -93,6 +93,10 @@ def main():
     ap.add_argument("--acc", default="dd", choices=["dd", "fp64"])
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-chain", action="store_true",
+                    help="skip the 4096-problem chain-rule forward (N = 20..40 submatrices)")
+    ap.add_argument("--no-modes", action="store_true",
+                    help="skip the forward precision-mode table (ET/FDS x FP64/DD)")
     ap.add_argument("--no-store", action="store_true",
                     help="recompute the per-term coefficients in the backward instead of keeping "
                          "the forward's coefficient store")
@@ -105,6 +109,7 @@ def main():
     import torch
     from paper_2108_01622_amd import api, inputs
     from paper_2108_01622_amd import _binding
+    from paper_2108_01622_amd.profiling import stored_traffic
 
     dev = torch.device("cuda", 0)
     A_np, g_np = inputs.grad40(count=args.batch)
@@ -181,12 +186,12 @@ def main():
         bwd_tf = bwd_flops * terms / bwd_s / 1e12
         dom = {"bound": "alu", "kernel": "backward_kernel<5>", "achieved": bwd_tf,
                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": bwd_tf / FP64_PEAK_TFLOPS,
-               "traffic": None, "per_term_flops": bwd_flops,
+               "traffic": stored_traffic("backward_kernel<5>", terms), "per_term_flops": bwd_flops,
                "terms_per_launch": terms, "launch_ms": bwd_s * 1e3}
     else:
         dom = {"bound": "alu", "kernel": "forward_kernel<5>", "achieved": fwd_tf,
                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": fwd_tf / FP64_PEAK_TFLOPS,
-               "traffic": None, "per_term_flops": canonical_flops(m, n),
+               "traffic": stored_traffic("forward_kernel<5>", terms), "per_term_flops": canonical_flops(m, n),
                "terms_per_launch": terms, "launch_ms": fwd_s * 1e3}
     res = {
         "metric": "lhaf terms/sec (N=40, FDS, double-double; " +
@@ -208,6 +213,8 @@ def main():
                    "sum": args.sum, "acc": args.acc,
                    "backward_coefficients": "forward store" if store is not None else "recomputed"},
         "roofline": dom,
+        "lhafs_per_s": args.batch * args.steps / elapsed,
+        "time_to_solution_s": elapsed / args.steps,
         "forward": {"kernel": "forward_kernel<5>", "terms_per_s": terms / fwd_s, "tflops": fwd_tf,
                     "frac": fwd_tf / FP64_PEAK_TFLOPS, "launch_ms": fwd_s * 1e3,
                     "per_term_flops": canonical_flops(m, n)},
@@ -259,6 +266,42 @@ def main():
                 ent["oracle"] = "__float128 FDS of both halves, multiplied"
         res["n52_forward"] = ent
         print("[bench] N=52 done", file=sys.stderr, flush=True)
+    if not args.no_modes:
+        # forward precision modes on the first 8 matrices of the batch
+        A8, g8 = A[:8], g[:8]
+        modes = {}
+        for sm in ("fds", "et"):
+            for am in ("dd", "fp64"):
+                api.lhaf_batched(A8, g8, sum=sm, acc=am)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                api.lhaf_batched(A8, g8, sum=sm, acc=am)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t
+                T8 = 8 * _binding.term_count(N, sum=sm)
+                modes[f"{sm}/{am}"] = {"terms_per_s": T8 / dt, "lhafs_per_s": 8 / dt,
+                                       "frac": canonical_flops(m, n) * T8 / dt / 1e12 / FP64_PEAK_TFLOPS}
+        res["forward_modes_n40"] = modes
+        print("[bench] precision modes done", file=sys.stderr, flush=True)
+    if not args.no_chain:
+        # chain-rule batch: 4096 submatrices N = 20..40 of the 100-mode state, one launch
+        ch = inputs.chain4096()
+        Bc = torch.as_tensor(ch["B"], device=dev)
+        gc = torch.as_tensor(ch["gamma"], device=dev)
+        api.lhaf_batched(Bc, gc, idx=ch["idx"][:ch["idx_off"][64]], idx_off=ch["idx_off"][:65])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        api.lhaf_batched(Bc, gc, idx=ch["idx"], idx_off=ch["idx_off"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        Tc = sum(_binding.term_count(int(k)) for k in ch["sizes"])
+        fl = sum(_binding.term_count(int(k)) * canonical_flops(int(k), int(k) // 2) for k in ch["sizes"])
+        res["chain4096_forward"] = {"workload": "4096 submatrices N=20..40 (even) of the 100-mode state, "
+                                                "FDS dd, one persistent launch",
+                                    "terms": Tc, "seconds": dt, "terms_per_s": Tc / dt,
+                                    "lhafs_per_s": 4096 / dt, "tflops": fl / dt / 1e12,
+                                    "frac": fl / dt / 1e12 / FP64_PEAK_TFLOPS}
+        print("[bench] chain4096 done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(A_np[0], g_np[0])
     print(json.dumps(res), flush=True)
