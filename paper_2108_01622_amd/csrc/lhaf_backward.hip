@@ -65,8 +65,8 @@ __device__ __forceinline__ void lane_sync() {
 __device__ __forceinline__ cd* lds_x(const LdsView& L) { return L.ring + L.NP * L.NR; }
 
 // R <- R * M with R in registers (lane (p,q) holds R[8a+p][8k+q]) and M
-// row-major LD x LD (LDS or global).  Output row i needs only input row i,
-// so rows are done in groups of G local rows, in place: only the group's
+// row-major LD x LD (global).  Output row i needs only input row i, so rows
+// are done in groups of G local rows, in place: only the group's
 // accumulators are live, and M is streamed once per group.
 template <int B, int G, int A0>
 __device__ __forceinline__ void mul_rows(double (&Rr)[B][B], double (&Ri)[B][B],
@@ -109,6 +109,64 @@ __device__ __forceinline__ void mul_rows(double (&Rr)[B][B], double (&Ri)[B][B],
       }
     mul_rows<B, G, A0 + G>(Rr, Ri, M, p, q);
   }
+}
+
+// Row l of the product O += R[:, l] M[l, :] with compile-time l: R[8a+p][l]
+// reaches the row group by a DPP broadcast from lane (p, l mod 8), with no
+// LDS round trip; the operand row of M for l + 1 is fetched while row l is
+// used, and a scheduling barrier keeps the live operands to two rows.
+template <int B, int L>
+__device__ __forceinline__ void product_rows(const double (&Rr)[B][B], const double (&Ri)[B][B],
+                                             double (&Or)[B][B], double (&Oi)[B][B],
+                                             cd (&mrow)[B], const cd* __restrict__ M,
+                                             const int q) {
+  constexpr int LD = 8 * B;
+  if constexpr (L < LD) {
+    constexpr int b = L / 8, r = L % 8;
+    cd mnext[B];
+    if constexpr (L + 1 < LD) {
+#pragma unroll
+      for (int k = 0; k < B; ++k) mnext[k] = M[(L + 1) * LD + 8 * k + q];
+    }
+#pragma unroll
+    for (int a = 0; a < B; ++a) {
+      const cd x = mk(bcast_row8_c<r>(Rr[a][b]), bcast_row8_c<r>(Ri[a][b]));
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const cd o = cfma(x, mrow[k], mk(Or[a][k], Oi[a][k]));
+        Or[a][k] = o.r;
+        Oi[a][k] = o.i;
+      }
+    }
+    if constexpr (L + 1 < LD) {
+#pragma unroll
+      for (int k = 0; k < B; ++k) mrow[k] = mnext[k];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    product_rows<B, L + 1>(Rr, Ri, Or, Oi, mrow, M, q);
+  }
+}
+
+// R <- R * M for the LDS-staged tiles: all output rows at once, M read once.
+template <int B>
+__device__ __forceinline__ void mul_right_dpp(double (&Rr)[B][B], double (&Ri)[B][B],
+                                              const cd* __restrict__ M, const int q) {
+  double Or[B][B], Oi[B][B];
+#pragma unroll
+  for (int a = 0; a < B; ++a)
+#pragma unroll
+    for (int k = 0; k < B; ++k) Or[a][k] = Oi[a][k] = 0.0;
+  cd mrow[B];
+#pragma unroll
+  for (int k = 0; k < B; ++k) mrow[k] = M[8 * k + q];
+  product_rows<B, 0>(Rr, Ri, Or, Oi, mrow, M, q);
+#pragma unroll
+  for (int a = 0; a < B; ++a)
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      Rr[a][k] = Or[a][k];
+      Ri[a][k] = Oi[a][k];
+    }
 }
 
 // row-group size per tile: bounded accumulator footprint
@@ -232,6 +290,45 @@ __device__ __forceinline__ void accumulate_g(cd* __restrict__ G, const double co
   }
 }
 
+// R <- B_q (reset) or R + B_q, B_q = a_{qs+1} I + sum_{r=1..s-1} a_{qs+r+1} W^r
+// with W^r read from the wavefront scratch (one row block per batch of loads).
+template <int B>
+__device__ __forceinline__ void combine_powers(double (&Rr)[B][B], double (&Ri)[B][B],
+                                               const bool reset, const cd* __restrict__ pw,
+                                               const cd* __restrict__ acoef, const int qq,
+                                               const int s, const int n, const int m,
+                                               const int p, const int q) {
+  constexpr int LD = 8 * B;
+  const cd ak = acoef[qq * s + 1];
+#pragma unroll
+  for (int a = 0; a < B; ++a)
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const int i = 8 * a + p, c = 8 * k + q;
+      if (reset) Rr[a][k] = Ri[a][k] = 0.0;
+      if (i == c && i < m) {
+        Rr[a][k] += ak.r;
+        Ri[a][k] += ak.i;
+      }
+    }
+  for (int r = 1; r < s && qq * s + r + 1 <= n; ++r) {
+    const cd a1 = acoef[qq * s + r + 1];
+    const cd* P1 = pw + (r - 1) * LD * LD;
+#pragma unroll
+    for (int a = 0; a < B; ++a) {
+      cd x1[B];
+#pragma unroll
+      for (int k = 0; k < B; ++k) x1[k] = P1[(8 * a + p) * LD + 8 * k + q];
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const cd o = cfma(a1, x1[k], mk(Rr[a][k], Ri[a][k]));
+        Rr[a][k] = o.r;
+        Ri[a][k] = o.i;
+      }
+    }
+  }
+}
+
 // Gradient of the terms [t0, t1) of problem P into the item slot
 // G[LD*LD] (accumulated as sum_t c_t d_{pair(j)} M_t[j][c], M = (d f/d W)^T)
 // and G[LD*LD + l] (d f / d v_l).  With a coefficient store written by the
@@ -327,63 +424,31 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
     // re-read from L2 (the pointer is hidden from the optimiser so it does
     // not keep the first copy live through the Hessenberg phase).
     const cd* Cp2 = launder_ptr(Cp);
-    load_w<B>(Cp2, dcol, p, q, Wr, Wi);
-    if (kStage) store_mat<B>(Wr, Wi, X, p, q);
-    if (s > 1) store_mat<B>(Wr, Wi, pw, p, q);  // W^1
+    load_w<B>(Cp2, dcol, p, q, Rr, Ri);
+    if (kStage) store_mat<B>(Rr, Ri, X, p, q);
+    if (s > 1) store_mat<B>(Rr, Ri, pw, p, q);  // W^1
     lane_sync<kStage>();
     const cd* Wop = kStage ? X : pw;
     cd* Yop = kStage ? X : pw + (s - 1) * LD * LD;
-    for (int e = 2; e <= s; ++e) {
-      mul_right<B>(Wr, Wi, Wop, p, q);  // W^e = W^{e-1} W
-      if (e == s) lane_sync<kStage>();  // every read of W precedes its overwrite
-      store_mat<B>(Wr, Wi, e < s ? pw + (e - 1) * LD * LD : Yop, p, q);
-      lane_sync<kStage>();
-    }
-    // R = B_Q, then R <- R W^s + B_q for q = Q-1 .. 0, where
-    // B_q = sum_{r=0..s-1} a_{qs+r+1} W^r
-#pragma unroll
-    for (int a = 0; a < B; ++a)
-#pragma unroll
-      for (int k = 0; k < B; ++k) Rr[a][k] = Ri[a][k] = 0.0;
-    for (int qq = Q; qq >= 0; --qq) {
-      if (qq != Q) mul_right<B>(Rr, Ri, Yop, p, q);
-      // + a_{qs+1} I
-      {
-        const cd ak = acoef[qq * s + 1];
-#pragma unroll
-        for (int a = 0; a < B; ++a)
-#pragma unroll
-          for (int k = 0; k < B; ++k) {
-            const int i = 8 * a + p, c = 8 * k + q;
-            if (i == c && i < m) {
-              Rr[a][k] += ak.r;
-              Ri[a][k] += ak.i;
-            }
-          }
-      }
-      // + sum_{r=1..s-1} a_{qs+r+1} W^r, two powers per batch of loads
-      for (int r = 1; r < s && qq * s + r + 1 <= n; r += 2) {
-        const bool two = r + 1 < s && qq * s + r + 2 <= n;
-        const cd a1 = acoef[qq * s + r + 1];
-        const cd a2 = two ? acoef[qq * s + r + 2] : czero();
-        const cd* P1 = pw + (r - 1) * LD * LD;
-        const cd* P2 = two ? P1 + LD * LD : P1;
-        cd x1[B][B], x2[B][B];
-#pragma unroll
-        for (int a = 0; a < B; ++a)
-#pragma unroll
-          for (int k = 0; k < B; ++k) {
-            x1[a][k] = P1[(8 * a + p) * LD + 8 * k + q];
-            x2[a][k] = P2[(8 * a + p) * LD + 8 * k + q];
-          }
-#pragma unroll
-        for (int a = 0; a < B; ++a)
-#pragma unroll
-          for (int k = 0; k < B; ++k) {
-            const cd o = cfma(a2, x2[a][k], cfma(a1, x1[a][k], mk(Rr[a][k], Ri[a][k])));
-            Rr[a][k] = o.r;
-            Ri[a][k] = o.i;
-          }
+    // One product per step (a single call site keeps the unrolled product
+    // code once): steps 0..s-2 form W^2..W^s (R = W^{step+2}); then R = B_Q
+    // and steps s-1 .. s-2+Q are the Horner steps R <- R W^s + B_q,
+    // q = Q-1 .. 0, where B_q = sum_{r=0..s-1} a_{qs+r+1} W^r.
+    if (s == 1) combine_powers<B>(Rr, Ri, true, pw, acoef, Q, s, n, m, p, q);
+    const int nsteps = (s - 1) + Q;
+    for (int step = 0; step < nsteps; ++step) {
+      if constexpr (kStage) mul_right_dpp<B>(Rr, Ri, X, q);
+      else mul_right<B>(Rr, Ri, step < s - 1 ? Wop : Yop, p, q);
+      if (step < s - 2) {
+        store_mat<B>(Rr, Ri, pw + (step + 1) * LD * LD, p, q);  // W^{step+2}
+        lane_sync<kStage>();
+      } else if (step == s - 2) {
+        lane_sync<kStage>();  // every read of W precedes its overwrite
+        store_mat<B>(Rr, Ri, Yop, p, q);
+        lane_sync<kStage>();
+        combine_powers<B>(Rr, Ri, true, pw, acoef, Q, s, n, m, p, q);
+      } else {
+        combine_powers<B>(Rr, Ri, false, pw, acoef, Q - 1 - (step - (s - 1)), s, n, m, p, q);
       }
     }
     accumulate_g<B>(G, coef, drow, Rr, Ri, p, q);

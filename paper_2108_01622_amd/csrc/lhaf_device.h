@@ -94,6 +94,29 @@ __device__ __forceinline__ cd sum_row8(cd a) { return mk(sum_row8(a.r), sum_row8
 __device__ __forceinline__ cd sum_col8(cd a) { return mk(sum_col8(a.r), sum_col8(a.i)); }
 __device__ __forceinline__ cd sum_xor32(cd a) { return mk(sum_xor32(a.r), sum_xor32(a.i)); }
 
+// Value of lane 8p + r for every lane of row group p (r compile-time): DPP
+// row_newbcast broadcasts one lane of each 16-lane row; the bank masks write
+// lane r into the lower half-row (group 2j) and lane 8 + r into the upper
+// half-row (group 2j + 1).
+template <int R>
+__device__ __forceinline__ double bcast_row8_c(double x) {
+  double y = __builtin_amdgcn_update_dpp(x, x, 0x150 + R, 0xF, 0x3, false);
+  return __builtin_amdgcn_update_dpp(y, x, 0x158 + R, 0xF, 0xC, false);
+}
+// same with r folded to a constant by full unrolling of the caller's loop
+__device__ __forceinline__ double bcast_row8(double x, const int r) {
+  switch (r) {
+    case 0: return bcast_row8_c<0>(x);
+    case 1: return bcast_row8_c<1>(x);
+    case 2: return bcast_row8_c<2>(x);
+    case 3: return bcast_row8_c<3>(x);
+    case 4: return bcast_row8_c<4>(x);
+    case 5: return bcast_row8_c<5>(x);
+    case 6: return bcast_row8_c<6>(x);
+    default: return bcast_row8_c<7>(x);
+  }
+}
+
 __device__ __forceinline__ double shfl_d(double x, int src) {
   int lo = __double2loint(x), hi = __double2hiint(x);
   lo = __builtin_amdgcn_ds_bpermute(src << 2, lo);
