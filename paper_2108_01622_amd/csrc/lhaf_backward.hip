@@ -113,37 +113,42 @@ __device__ __forceinline__ void mul_rows(double (&Rr)[B][B], double (&Ri)[B][B],
 
 // Row l of the product O += R[:, l] M[l, :] with compile-time l: R[8a+p][l]
 // reaches the row group by a DPP broadcast from lane (p, l mod 8), with no
-// LDS round trip; the operand row of M for l + 1 is fetched while row l is
-// used, and a scheduling barrier keeps the live operands to two rows.
+// LDS round trip; the operand row of M for l + 1 is fetched into the other
+// buffer while row l is used, and a scheduling barrier keeps the live
+// operands to two rows.
 template <int B, int L>
 __device__ __forceinline__ void product_rows(const double (&Rr)[B][B], const double (&Ri)[B][B],
                                              double (&Or)[B][B], double (&Oi)[B][B],
-                                             cd (&mrow)[B], const cd* __restrict__ M,
-                                             const int q) {
+                                             cd (&mcur)[B], cd (&mnxt)[B],
+                                             const cd* __restrict__ M, const int q) {
   constexpr int LD = 8 * B;
   if constexpr (L < LD) {
     constexpr int b = L / 8, r = L % 8;
-    cd mnext[B];
     if constexpr (L + 1 < LD) {
 #pragma unroll
-      for (int k = 0; k < B; ++k) mnext[k] = M[(L + 1) * LD + 8 * k + q];
+      for (int k = 0; k < B; ++k) mnxt[k] = M[(L + 1) * LD + 8 * k + q];
+    }
+    double xr[B], xi[B];
+#pragma unroll
+    for (int a = 0; a < B; ++a) {
+      xr[a] = bcast_row8_lo<r>(Rr[a][b]);
+      xi[a] = bcast_row8_lo<r>(Ri[a][b]);
     }
 #pragma unroll
     for (int a = 0; a < B; ++a) {
-      const cd x = mk(bcast_row8_c<r>(Rr[a][b]), bcast_row8_c<r>(Ri[a][b]));
+      xr[a] = bcast_row8_hi<r>(xr[a], Rr[a][b]);
+      xi[a] = bcast_row8_hi<r>(xi[a], Ri[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < B; ++a)
 #pragma unroll
       for (int k = 0; k < B; ++k) {
-        const cd o = cfma(x, mrow[k], mk(Or[a][k], Oi[a][k]));
+        const cd o = cfma(mk(xr[a], xi[a]), mcur[k], mk(Or[a][k], Oi[a][k]));
         Or[a][k] = o.r;
         Oi[a][k] = o.i;
       }
-    }
-    if constexpr (L + 1 < LD) {
-#pragma unroll
-      for (int k = 0; k < B; ++k) mrow[k] = mnext[k];
-    }
     __builtin_amdgcn_sched_barrier(0);
-    product_rows<B, L + 1>(Rr, Ri, Or, Oi, mrow, M, q);
+    product_rows<B, L + 1>(Rr, Ri, Or, Oi, mnxt, mcur, M, q);
   }
 }
 
@@ -156,10 +161,10 @@ __device__ __forceinline__ void mul_right_dpp(double (&Rr)[B][B], double (&Ri)[B
   for (int a = 0; a < B; ++a)
 #pragma unroll
     for (int k = 0; k < B; ++k) Or[a][k] = Oi[a][k] = 0.0;
-  cd mrow[B];
+  cd m0[B], m1[B];
 #pragma unroll
-  for (int k = 0; k < B; ++k) mrow[k] = M[8 * k + q];
-  product_rows<B, 0>(Rr, Ri, Or, Oi, mrow, M, q);
+  for (int k = 0; k < B; ++k) m0[k] = M[8 * k + q];
+  product_rows<B, 0>(Rr, Ri, Or, Oi, m0, m1, M, q);
 #pragma unroll
   for (int a = 0; a < B; ++a)
 #pragma unroll

@@ -98,9 +98,21 @@ __device__ __forceinline__ cd sum_xor32(cd a) { return mk(sum_xor32(a.r), sum_xo
 // row_newbcast broadcasts one lane of each 16-lane row; the bank masks write
 // lane r into the lower half-row (group 2j) and lane 8 + r into the upper
 // half-row (group 2j + 1).
+// (The lanes the first move leaves unwritten are written by the second, so
+// the first needs no old value and no copy of x.)
 template <int R>
 __device__ __forceinline__ double bcast_row8_c(double x) {
-  double y = __builtin_amdgcn_update_dpp(x, x, 0x150 + R, 0xF, 0x3, false);
+  double y = __builtin_amdgcn_mov_dpp(x, 0x150 + R, 0xF, 0x3, false);
+  return __builtin_amdgcn_update_dpp(y, x, 0x158 + R, 0xF, 0xC, false);
+}
+// The two halves of bcast_row8_c separately, so that a caller can issue all
+// first halves before the second ones (the second reads the first's result).
+template <int R>
+__device__ __forceinline__ double bcast_row8_lo(double x) {
+  return __builtin_amdgcn_mov_dpp(x, 0x150 + R, 0xF, 0x3, false);
+}
+template <int R>
+__device__ __forceinline__ double bcast_row8_hi(double y, double x) {
   return __builtin_amdgcn_update_dpp(y, x, 0x158 + R, 0xF, 0xC, false);
 }
 // same with r folded to a constant by full unrolling of the caller's loop
