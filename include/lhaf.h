@@ -150,6 +150,32 @@ lh_status lhaf_batched(int32_t B, const lh_c128* A_base, int64_t lda, int64_t st
                        const int64_t* idx_off, const int32_t* r, lh_c128* out, double* err_est,
                        void* workspace, size_t ws_bytes, const lh_opts* opts, void* stream);
 
+/* One chain-rule step (App. B.5, batching over the batched mode's outcome):
+ * out[k] = lhaf(A_{r(k)}, gamma_{r(k)}), k = 0..n_cut, where r(k) is the host
+ * pattern r (M entries, r[mode_b] must be 0) with mode_b set to k photons.
+ * One pass over the ET terms of the largest pattern (mode_b paired with
+ * itself floor(n_cut/2) times and once with a padding vertex) serves every
+ * output: the power traces are shared, each output takes its own binomial
+ * weights and lambda degree.  Requires opts->sum = LH_SUM_ET (else
+ * LH_EUNSUPPORTED); sum(r) + n_cut <= 64 and n_cut <= 63.  A, gamma: device,
+ * M x M (lda) and M; out: device [n_cut+1]; err_est: device [n_cut+1] or NULL.
+ * opts->workspace, if set, needs at least the bytes of the equivalent
+ * lhaf_repeated call plus (n_cut+1) partials per work item; NULL uses the
+ * library buffer. */
+lh_status lhaf_chain(const lh_c128* A, int64_t lda, const lh_c128* gamma, const int32_t* r,
+                     int32_t M, int32_t mode_b, int32_t n_cut, lh_c128* out, double* err_est,
+                     const lh_opts* opts, void* stream);
+
+/* Sub-detector batching (App. B.5): out[g] = lhaf(A_r, gamma_g) for G loop
+ * weight vectors gamma_g = gammas + g*ldg (device, M entries each) of one
+ * matrix (r: HOST multiplicities or NULL = plain M x M).  The Hessenberg and
+ * characteristic-polynomial work of each term is done once; the loop moments
+ * and exponential series once per vector.  ET or FDS; 1 <= G <= 64.
+ * out, err_est: device [G]. */
+lh_status lhaf_gammas(const lh_c128* A, int64_t lda, const lh_c128* gammas, int64_t ldg,
+                      const int32_t* r, int32_t M, int32_t G, lh_c128* out, double* err_est,
+                      const lh_opts* opts, void* stream);
+
 /* Entries (lh_c128) of the per-term coefficient store of the batch for
  * opts->sum: sum over problems of terms x n.  Host only; a negative value is
  * -lh_status. */

@@ -256,6 +256,32 @@ def lhaf_repeated(A, g, r, method="sum", **kw):
     return lhaf_sum(A2, g2, ps, **kw)
 
 
+def lhaf_chain_outputs(A, g, r, mode_b, n_cut, method="explicit", **kw):
+    """Outputs of one chain-rule step by their definition (App. B.5): lhaf of
+    the pattern r with mode_b set to k photons, for k = 0..n_cut."""
+    out = []
+    for k in range(n_cut + 1):
+        rk = np.array(r, dtype=np.int64).copy()
+        rk[mode_b] = k
+        out.append(lhaf_repeated(A, g, rk, method=method, **kw) if rk.sum() > 0 else 1.0 + 0j)
+    return np.array(out, dtype=np.complex128)
+
+
+def lhaf_gamma_outputs(A, gammas, r=None, method="explicit", **kw):
+    """Sub-detector outputs by their definition (App. B.5): lhaf(A_r, gamma_g)
+    for every row gamma_g of gammas (r = None: the plain matrix)."""
+    out = []
+    for gv in np.asarray(gammas):
+        if r is None:
+            if method == "explicit":
+                out.append(lhaf_memo(A, gv, prec=kw.get("prec", "f64")))
+            else:
+                out.append(lhaf_sum(A, gv, **kw))
+        else:
+            out.append(lhaf_repeated(A, gv, r, method=method, **kw))
+    return np.array(out, dtype=np.complex128)
+
+
 # ---------------------------------------------------------------------------
 # numpy: traces from eigenvalues (the route App. B.1 names), batched
 def _digits(t, radix):

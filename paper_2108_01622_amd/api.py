@@ -106,6 +106,49 @@ def lhaf_batched_workspace(idx_off, r=None, **kw) -> int:
                                                ctypes.byref(o)))
 
 
+def lhaf_chain(A, gamma, r, mode_b: int, n_cut: int, *, acc="dd", schedule=-1,
+               return_error=False, workspace=None):
+    """One chain-rule step: out[k] = lhaf of the pattern r with mode_b at k
+    photons, k = 0..n_cut (ET sum; one pass serves every k).  r: host ints,
+    one per row of A, r[mode_b] = 0."""
+    A = _dev_c128(A, "A")
+    gamma = _dev_c128(gamma, "gamma")
+    M = A.shape[0]
+    rr = np.ascontiguousarray(np.asarray(r), dtype=np.int32)
+    if A.dim() != 2 or A.shape[1] != M or gamma.shape != (M,) or len(rr) != M:
+        raise ValueError("A (M,M), gamma (M,) and r (M,) required")
+    out = torch.empty(n_cut + 1, dtype=torch.complex128, device=A.device)
+    err = torch.empty(n_cut + 1, dtype=torch.float64, device=A.device)
+    o = Bn.make_opts("et", acc, 0, -1, True, schedule, workspace)
+    with torch.cuda.device(A.device):
+        Bn.check(Bn.lib().lhaf_chain(_p(A), M, _p(gamma), Bn.host_ptr(rr), M, int(mode_b),
+                                     int(n_cut), _p(out), _p(err), ctypes.byref(o),
+                                     _stream_ptr(A.device)))
+    return (out, err) if return_error else out
+
+
+def lhaf_gammas(A, gammas, r=None, *, sum="fds", acc="dd", schedule=-1, return_error=False,
+                workspace=None):
+    """Sub-detector batching: out[g] = lhaf(A_r, gammas[g]) for G <= 64 loop
+    weight vectors (gammas (G, M)) of one matrix, one pass over the terms."""
+    A = _dev_c128(A, "A")
+    gammas = _dev_c128(gammas, "gammas")
+    M = A.shape[0]
+    if A.dim() != 2 or A.shape[1] != M or gammas.dim() != 2 or gammas.shape[1] != M:
+        raise ValueError("A (M,M) and gammas (G,M) required")
+    G = gammas.shape[0]
+    rr = None if r is None else np.ascontiguousarray(np.asarray(r), dtype=np.int32)
+    if rr is not None and len(rr) != M:
+        raise ValueError("r must have one entry per row of A")
+    out = torch.empty(G, dtype=torch.complex128, device=A.device)
+    err = torch.empty(G, dtype=torch.float64, device=A.device)
+    o = Bn.make_opts(sum, acc, 0, -1, True, schedule, workspace)
+    with torch.cuda.device(A.device):
+        Bn.check(Bn.lib().lhaf_gammas(_p(A), M, _p(gammas), M, Bn.host_ptr(rr), M, G, _p(out),
+                                      _p(err), ctypes.byref(o), _stream_ptr(A.device)))
+    return (out, err) if return_error else out
+
+
 def lhaf_saved_count(idx_off, r=None, sum="fds") -> int:
     """Entries of the per-term coefficient store of a batch (complex128)."""
     off = np.ascontiguousarray(idx_off, dtype=np.int64)

@@ -18,6 +18,7 @@
 // kernels (one translation unit with the launches)
 #include "lhaf_forward.hip"
 #include "lhaf_backward.hip"
+#include "lhaf_multi.hip"
 
 namespace lh {
 
@@ -605,6 +606,90 @@ lh_status lhaf_repeated(const lh_c128* A, int64_t lda, const lh_c128* gamma, con
                       o.ws_bytes, o, (hipStream_t)stream, false, nullptr);
 }
 
+// One problem, several outputs (chain-rule step or loop-weight vectors).
+static lh_status multi_impl(const PairPlan& plan, const lh_c128* A, int64_t lda,
+                            const lh_c128* gamma, const lh_c128* gammas, int64_t ldg,
+                            MultiArgs ma, lh_c128* out, double* err, const lh_opts& o,
+                            hipStream_t st) {
+  int dev = 0;
+  lh_status s = ensure_device(dev);
+  if (s != LH_OK) return s;
+  std::vector<ProblemIn> pin(1);
+  pin[0].plan = plan;
+  pin[0].a_off = pin[0].g_off = pin[0].i_off = 0;
+  Plan pl;
+  s = build_plan(pin, o, dev, pl, false);
+  if (s != LH_OK) return s;
+  if (pl.probs[0].n > 32) return LH_ESIZE;
+  const size_t parts_bytes = sizeof(Partial) * (size_t)std::max<size_t>(pl.items.size(), 1) * ma.nout;
+  const size_t off_parts = pl.lay.total;
+  const size_t off_vg = align_up(off_parts + parts_bytes);
+  const size_t total = align_up(off_vg + sizeof(cd) * 64 * (size_t)(ma.mode == 1 ? ma.nout : 1));
+  void* ws = o.workspace;
+  std::unique_lock<std::mutex> lk(g_mu, std::defer_lock);
+  if (!ws) {
+    lk.lock();
+    s = get_scratch(dev, total, &ws);
+    if (s != LH_OK) return s;
+  } else if (o.ws_bytes < total) {
+    return LH_ENOMEM;
+  }
+  char* base = static_cast<char*>(ws);
+  s = upload_plan(pl, base, st, dev);
+  if (s != LH_OK) return s;
+  hipLaunchKernelGGL(pack_kernel, dim3(1), dim3(256), 0, st,
+                     reinterpret_cast<const Prob*>(base + pl.lay.probs),
+                     reinterpret_cast<const int64_t*>(base + pl.lay.aoff),
+                     reinterpret_cast<const int64_t*>(base + pl.lay.goff),
+                     reinterpret_cast<const int64_t*>(base + pl.lay.ioff), A, lda, gamma, nullptr,
+                     reinterpret_cast<cd*>(base + pl.lay.cdata),
+                     reinterpret_cast<int*>(base + pl.lay.counter));
+  if (hipGetLastError() != hipSuccess) return LH_EHIP;
+  cd* vg = reinterpret_cast<cd*>(base + off_vg);
+  if (ma.mode == 1) {
+    hipLaunchKernelGGL(pack_gammas_kernel, dim3((64 * ma.nout + 255) / 256), dim3(256), 0, st,
+                       reinterpret_cast<const Prob*>(base + pl.lay.probs), gammas, ldg, ma.nout, vg);
+    if (hipGetLastError() != hipSuccess) return LH_EHIP;
+    ma.vg = vg;
+  }
+  Partial* parts = reinterpret_cast<Partial*>(base + off_parts);
+  const int acc_dd = o.acc == LH_ACC_DD ? 1 : 0;
+  if (!pl.items.empty()) {
+    const int nmax = std::max(pl.nmax, 1);
+    const size_t lds = multi_lds_bytes(nmax, ma.mode, ma.nout);
+#define LH_MLAUNCH(BB)                                                                         \
+  if (ma.mode == 1)                                                                            \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(multi_kernel<BB, 1>), dim3(pl.grid), dim3(64), lds, st, \
+                       reinterpret_cast<const Prob*>(base + pl.lay.probs),                     \
+                       reinterpret_cast<const Item*>(base + pl.lay.items), (int)pl.items.size(), \
+                       reinterpret_cast<int*>(base + pl.lay.counter),                          \
+                       reinterpret_cast<const cd*>(base + pl.lay.cdata), parts, acc_dd, nmax, ma); \
+  else                                                                                         \
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(multi_kernel<BB, 0>), dim3(pl.grid), dim3(64), lds, st,   \
+                     reinterpret_cast<const Prob*>(base + pl.lay.probs),                       \
+                     reinterpret_cast<const Item*>(base + pl.lay.items), (int)pl.items.size(), \
+                     reinterpret_cast<int*>(base + pl.lay.counter),                            \
+                     reinterpret_cast<const cd*>(base + pl.lay.cdata), parts, acc_dd, nmax, ma)
+    switch (pl.bmax) {
+      case 1: LH_MLAUNCH(1); break;
+      case 2: LH_MLAUNCH(2); break;
+      case 3: LH_MLAUNCH(3); break;
+      case 4: LH_MLAUNCH(4); break;
+      case 5: LH_MLAUNCH(5); break;
+      case 6: LH_MLAUNCH(6); break;
+      case 7: LH_MLAUNCH(7); break;
+      default: LH_MLAUNCH(8); break;
+    }
+#undef LH_MLAUNCH
+    if (hipGetLastError() != hipSuccess) return LH_EHIP;
+  }
+  hipLaunchKernelGGL(finalize_multi_kernel, dim3(1), dim3(64), 0, st,
+                     reinterpret_cast<const Prob*>(base + pl.lay.probs), parts, ma, out, err,
+                     acc_dd);
+  if (hipGetLastError() != hipSuccess) return LH_EHIP;
+  return LH_OK;
+}
+
 static lh_status backward_impl(int32_t B, const lh_c128* A_base, int64_t lda, int64_t stride_A,
                                const lh_c128* gamma_base, int64_t stride_g, const int32_t* idx,
                                const int64_t* idx_off, const int32_t* r, const lh_c128* grad_out,
@@ -696,6 +781,103 @@ static lh_status backward_impl(int32_t B, const lh_c128* A_base, int64_t lda, in
   }
   if (hipGetLastError() != hipSuccess) return LH_EHIP;
   return LH_OK;
+}
+
+lh_status lhaf_chain(const lh_c128* A, int64_t lda, const lh_c128* gamma, const int32_t* r,
+                     int32_t M, int32_t mode_b, int32_t n_cut, lh_c128* out, double* err_est,
+                     const lh_opts* opts, void* stream) {
+  lh_opts o;
+  lh_status s = validate_opts(opts, o);
+  if (s != LH_OK) return s;
+  if (o.sum != LH_SUM_ET) return LH_EUNSUPPORTED;
+  if (o.saved) return LH_EUNSUPPORTED;
+  if (M < 1 || !r || !out || !A || !gamma || lda < M || mode_b < 0 || mode_b >= M || n_cut < 0)
+    return LH_EINVAL;
+  if (M > kMaxRows) return LH_ESIZE;
+  int64_t tot = 0;
+  for (int i = 0; i < M; ++i) {
+    if (r[i] < 0) return LH_EINVAL;
+    if (i != mode_b) tot += r[i];
+  }
+  if (r[mode_b] != 0) return LH_EINVAL;
+  if (tot + n_cut > kMaxN || n_cut + 1 > 64) return LH_ESIZE;
+  PairPlan pp = plan_repeated(r, M);
+  const int nf = pp.n;
+  MultiArgs ma{};
+  ma.mode = 0;
+  ma.nout = n_cut + 1;
+  ma.nf = nf;
+  ma.pbb = ma.pbp = -1;
+  // append the batched mode: J self pairs, one pair with a padding vertex
+  std::vector<int> u(pp.pos.begin(), pp.pos.begin() + pp.H), w(pp.pos.begin() + pp.H, pp.pos.end());
+  const int J = n_cut / 2;
+  if (J >= 1) {
+    ma.pbb = (int)u.size();
+    u.push_back(mode_b);
+    w.push_back(mode_b);
+    pp.eta.push_back(J);
+  }
+  if (n_cut >= 1) {
+    ma.pbp = (int)u.size();
+    u.push_back(mode_b);
+    w.push_back(-1);
+    pp.eta.push_back(1);
+  }
+  pp.H = (int)u.size();
+  pp.n = 0;
+  for (int e : pp.eta) pp.n += e;
+  if (pp.H > kMaxPairs || 2 * pp.H > kMaxN || pp.n > 32) return LH_ESIZE;
+  pp.pos.assign(2 * pp.H, -1);
+  for (int p = 0; p < pp.H; ++p) {
+    pp.pos[p] = u[p];
+    pp.pos[pp.H + p] = w[p];
+  }
+  if (pp.H == 0) {  // nothing fixed, n_cut = 0: the empty pattern
+    int dev;
+    s = ensure_device(dev);
+    if (s != LH_OK) return s;
+    hipLaunchKernelGGL(fill_one_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, out, nullptr,
+                       err_est, 1);
+    return hipGetLastError() == hipSuccess ? LH_OK : LH_EHIP;
+  }
+  return multi_impl(pp, A, lda, gamma, nullptr, 0, ma, out, err_est, o, (hipStream_t)stream);
+}
+
+lh_status lhaf_gammas(const lh_c128* A, int64_t lda, const lh_c128* gammas, int64_t ldg,
+                      const int32_t* r, int32_t M, int32_t G, lh_c128* out, double* err_est,
+                      const lh_opts* opts, void* stream) {
+  lh_opts o;
+  lh_status s = validate_opts(opts, o);
+  if (s != LH_OK) return s;
+  if (o.saved) return LH_EUNSUPPORTED;
+  if (M < 0 || G < 1 || !out || (M > 0 && (!A || !gammas || lda < M || ldg < M))) return LH_EINVAL;
+  if (G > 64) return LH_ESIZE;
+  PairPlan pp;
+  if (r) {
+    int64_t tot = 0;
+    for (int i = 0; i < M; ++i) {
+      if (r[i] < 0) return LH_EINVAL;
+      tot += r[i];
+    }
+    if (tot > kMaxN || M > kMaxRows) return LH_ESIZE;
+    pp = plan_repeated(r, M);
+  } else {
+    if (M > kMaxN) return LH_ESIZE;
+    pp = plan_plain(M);
+  }
+  if (pp.n == 0) {
+    int dev;
+    s = ensure_device(dev);
+    if (s != LH_OK) return s;
+    hipLaunchKernelGGL(fill_one_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, out, nullptr,
+                       err_est, G);
+    return hipGetLastError() == hipSuccess ? LH_OK : LH_EHIP;
+  }
+  MultiArgs ma{};
+  ma.mode = 1;
+  ma.nout = G;
+  ma.pbb = ma.pbp = -1;
+  return multi_impl(pp, A, lda, gammas, gammas, ldg, ma, out, err_est, o, (hipStream_t)stream);
 }
 
 int64_t lhaf_saved_count(int32_t B, const int64_t* idx_off, const int32_t* r, const lh_opts* opts) {

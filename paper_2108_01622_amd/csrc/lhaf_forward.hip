@@ -388,6 +388,31 @@ __device__ __forceinline__ void loop_moments(const double (&Wr)[B][B], const dou
   }
 }
 
+// Two power-series recurrences at once, lanes 0..31 for (x0 -> y0) and lanes
+// 32..63 for (x1 -> y1), y[0] = 1 and
+//   k y_k = sum_{j=1..k} (al k + j/2) x_j y_{k-j},   k = 1..n:
+// al = -1 gives y = c(lambda)^{-1/2} from the coefficients c_j of
+// c(lambda) = det(I - lambda W); al = 0 gives y = exp(sum_j x_j lambda^j / 2).
+// Step k is a 32-lane dot product over j = 1..k (lane j-1 of the half)
+// reduced by a butterfly inside the half, so the serial chain is n steps.
+__device__ __forceinline__ void two_series(const cd* x0, cd* y0, const double al0, const cd* x1,
+                                           cd* y1, const double al1, const int n, const int lane) {
+  const int h = lane >> 5, j = (lane & 31) + 1;
+  const cd* xs = h == 0 ? x0 : x1;
+  cd* ys = h == 0 ? y0 : y1;
+  const cd xj = j <= n ? xs[j] : czero();
+  const double al = h == 0 ? al0 : al1;
+  if ((lane & 31) == 0) ys[0] = mk(1.0, 0.0);
+  wave_sync();
+  for (int k = 1; k <= n; ++k) {
+    cd t = czero();
+    if (j <= k) t = cmul(cscale(fma(al, (double)k, 0.5 * j), xj), ys[k - j]);
+    t = sum_half32(t);
+    if ((lane & 31) == 0) ys[k] = cscale(1.0 / k, t);
+    wave_sync();
+  }
+}
+
 // Hessenberg reduction (destroys W) and characteristic polynomial of W, then
 // the two series of f(lambda) = c(lambda)^{-1/2} exp(M(lambda)),
 // M = sum_k mu_k lambda^k / 2:
@@ -401,24 +426,8 @@ __device__ __forceinline__ void spectral_series(double (&Wr)[B][B], double (&Wi)
   wave_sync();
   cd pi = czero(), hsub = czero();
   HessLoop<B, 0>::run(Wr, Wi, m, n, p, q, lane, pi, hsub, L);
-  // Both series at once: lanes 0..31 build q, lanes 32..63 build L.  Step k
-  // is a 32-lane dot product over j = 1..k (lane j-1 of the half) reduced by
-  // a butterfly inside the half, so the serial chain is n steps long.
   const cd* cpoly = L.ring + ring_slot(m - 1, L.NR) * L.NP;
-  const int h = lane >> 5, j = (lane & 31) + 1;
-  const cd* xs = h == 0 ? cpoly : L.mu;
-  cd* ys = L.ser + 33 * h;
-  const cd xj = j <= n ? xs[j] : czero();
-  const double al = h == 0 ? -1.0 : 0.0;
-  if ((lane & 31) == 0) ys[0] = mk(1.0, 0.0);
-  wave_sync();
-  for (int k = 1; k <= n; ++k) {
-    cd t = czero();
-    if (j <= k) t = cmul(cscale(fma(al, (double)k, 0.5 * j), xj), ys[k - j]);
-    t = sum_half32(t);
-    if ((lane & 31) == 0) ys[k] = cscale(1.0 / k, t);
-    wave_sync();
-  }
+  two_series(cpoly, L.ser, -1.0, L.mu, L.ser + 33, 0.0, n, lane);
 }
 
 // Lane k (1 <= k <= n): a_k = e_{n-k} / 2, where e_j = sum_{i<=j} q_i L_{j-i}

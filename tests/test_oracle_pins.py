@@ -296,3 +296,45 @@ def test_row_expansion_and_affinity(orc):
     A2[j, i] += t
     slope = orc.lhaf_memo(*orc.remove(A, g, [i, j]), prec="f128")
     assert rel(orc.lhaf_memo(A2, g, prec="f128") - full, t * slope) < 1e-12
+
+
+def test_chain_outputs_single_mode_closed_form(orc):
+    """Chain-rule outputs (App. B.5) with nothing fixed: mode b alone at k
+    photons is the single-mode closed form sum_j C(k,2j)(2j-1)!! a^j g^(k-2j)."""
+    rng = np.random.Generator(np.random.PCG64(55))
+    A = rng.normal(size=(3, 3)) + 1j * rng.normal(size=(3, 3))
+    A = A + A.T
+    g = rng.normal(size=3) + 1j * rng.normal(size=3)
+    out = orc.lhaf_chain_outputs(A, g, [0, 0, 0], 1, 7, prec="f128")
+    for k in range(8):
+        want = orc.single_mode_repeated(A[1, 1], g[1], k)
+        assert abs(out[k] - want) <= 1e-12 * max(1.0, abs(want)), k
+
+
+def test_chain_outputs_factorise(orc):
+    """Batched mode uncoupled from the fixed modes: out[k] = lhaf(fixed) times
+    the single-mode value (block factorisation of lhaf)."""
+    rng = np.random.Generator(np.random.PCG64(56))
+    M = 4
+    A = rng.normal(size=(M, M)) + 1j * rng.normal(size=(M, M))
+    A = A + A.T
+    A[3, :3] = A[:3, 3] = 0.0
+    g = rng.normal(size=M) + 1j * rng.normal(size=M)
+    r = [2, 1, 2, 0]
+    fixed = orc.lhaf_repeated(A, g, r, method="explicit", prec="f128")
+    out = orc.lhaf_chain_outputs(A, g, r, 3, 5, prec="f128")
+    for k in range(6):
+        want = fixed * orc.single_mode_repeated(A[3, 3], g[3], k)
+        assert abs(out[k] - want) <= 1e-11 * abs(want), k
+
+
+def test_gamma_outputs_closed_forms(orc):
+    """Sub-detector outputs: N = 3 closed form for every loop vector."""
+    rng = np.random.Generator(np.random.PCG64(57))
+    A = rng.normal(size=(3, 3)) + 1j * rng.normal(size=(3, 3))
+    A = A + A.T
+    G = rng.normal(size=(4, 3)) + 1j * rng.normal(size=(4, 3))
+    out = orc.lhaf_gamma_outputs(A, G, prec="f128")
+    for k, g in enumerate(G):
+        want = g[0] * g[1] * g[2] + A[0, 1] * g[2] + A[0, 2] * g[1] + A[1, 2] * g[0]
+        assert abs(out[k] - want) <= 1e-13 * abs(want)
