@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-chain", action="store_true",
                     help="skip the 4096-problem chain-rule forward (N = 20..40 submatrices)")
+    ap.add_argument("--no-multi", action="store_true",
+                    help="skip the multi-output measurements (sub-detector and chain-rule batching)")
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the forward precision-mode table (ET/FDS x FP64/DD)")
     ap.add_argument("--no-store", action="store_true",
@@ -302,6 +304,44 @@ def main():
                                     "lhafs_per_s": 4096 / dt, "tflops": fl / dt / 1e12,
                                     "frac": fl / dt / 1e12 / FP64_PEAK_TFLOPS}
         print("[bench] chain4096 done", file=sys.stderr, flush=True)
+    if not args.no_multi:
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            return time.perf_counter() - t
+        # sub-detector batching: 12 loop-weight vectors of one N = 40 matrix
+        rng = np.random.Generator(np.random.PCG64(4040))
+        gs = g_np[0][None, :] + 0.05 * (rng.normal(size=(12, N)) + 1j * rng.normal(size=(12, N)))
+        gst = torch.as_tensor(gs, device=dev)
+        A12 = A[:1].expand(12, N, N).contiguous()
+        t_one = timed(lambda: api.lhaf_gammas(A[0], gst))
+        t_sep = timed(lambda: api.lhaf_batched(A12, gst))
+        res["gamma_batch_n40"] = {"workload": "one N=40 grad40 matrix, 12 loop-weight vectors, FDS dd",
+                                  "seconds": t_one, "separate_seconds": t_sep,
+                                  "speedup": t_sep / t_one,
+                                  "output_terms_per_s": 12 * terms_per_problem / t_one}
+        # chain-rule step: the 100-mode state's 40-photon pattern fixed, one
+        # empty mode batched up to 8 photons (9 outputs, ET)
+        st = inputs.state100(0)
+        rfix = st["r"].astype(np.int32).copy()
+        b = int(np.nonzero(rfix == 0)[0][0])
+        Bt = torch.as_tensor(st["B"], device=dev)
+        gt = torch.as_tensor(st["gamma"], device=dev)
+        t_chain = timed(lambda: api.lhaf_chain(Bt, gt, rfix, b, 8))
+        def separate():
+            for k in range(9):
+                rk = rfix.copy()
+                rk[b] = k
+                api.lhaf(Bt, gt, r=rk, sum="et")
+        t_sep = timed(separate)
+        res["chain_step_state100"] = {"workload": "state100 pattern (40 photons, 28 modes) fixed, "
+                                                  "one empty mode batched k = 0..8, ET dd",
+                                      "seconds": t_chain, "separate_seconds": t_sep,
+                                      "speedup": t_sep / t_chain}
+        print("[bench] multi-output done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(A_np[0], g_np[0])
     print(json.dumps(res), flush=True)
