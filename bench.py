@@ -341,6 +341,21 @@ def main():
                                                   "one empty mode batched k = 0..8, ET dd",
                                       "seconds": t_chain, "separate_seconds": t_sep,
                                       "speedup": t_sep / t_chain}
+        # mixed-state lhafmix (App. B.2): 2M x 2M with M = 20, N = 2 sum(n) <= 40
+        Am, gm, nm = inputs.mixed_state(20, 0)
+        while 2 * nm.sum() > 40:
+            nm[np.argmax(nm)] -= 1
+        Amt = torch.as_tensor(Am, device=dev)
+        gmt = torch.as_tensor(gm, device=dev)
+        t_mix = timed(lambda: api.lhaf_mixed(Amt, gmt, nm))
+        Tm = int(np.prod(nm[nm > 0] + 1))
+        Tm = Tm // 2 if np.any(nm % 2) else Tm // 2 + 1  # FDS halving (first odd pair, else pair 0)
+        t_greedy = timed(lambda: api.lhaf(Amt, gmt, r=np.concatenate([nm, nm])))
+        res["mixed_state_m20"] = {"workload": f"lhafmix, 2M x 2M with M = 20, n = {nm.tolist()}, "
+                                              f"N = {2 * int(nm.sum())}, FDS dd",
+                                  "seconds": t_mix, "greedy_repeated_seconds": t_greedy,
+                                  "terms": Tm,
+                                  "terms_per_s": Tm / t_mix}
         print("[bench] multi-output done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(A_np[0], g_np[0])

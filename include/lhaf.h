@@ -150,6 +150,16 @@ lh_status lhaf_batched(int32_t B, const lh_c128* A_base, int64_t lda, int64_t st
                        const int64_t* idx_off, const int32_t* r, lh_c128* out, double* err_est,
                        void* workspace, size_t ws_bytes, const lh_opts* opts, void* stream);
 
+/* Mixed-state form lhafmix(A, gamma, n) (App. B.2): A is 2M x 2M (device,
+ * lda >= 2M), gamma has 2M entries, n (HOST, M entries >= 0) gives the photon
+ * numbers; row i and row M+i are both repeated n_i times and paired with each
+ * other n_i times, so the sum has prod(n_i + 1) terms (ET) and pairs with
+ * n_i = 0 are dropped.  Equals lhaf_repeated on A with r = (n, n);
+ * 2 sum(n) <= 64.  Plain term ranges, the coefficient store and error
+ * estimates work as for lhaf. */
+lh_status lhaf_mixed(const lh_c128* A, int64_t lda, const lh_c128* gamma, const int32_t* n,
+                     int32_t M, lh_c128* out, double* err_est, const lh_opts* opts, void* stream);
+
 /* One chain-rule step (App. B.5, batching over the batched mode's outcome):
  * out[k] = lhaf(A_{r(k)}, gamma_{r(k)}), k = 0..n_cut, where r(k) is the host
  * pattern r (M entries, r[mode_b] must be 0) with mode_b set to k photons.

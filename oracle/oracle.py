@@ -256,6 +256,22 @@ def lhaf_repeated(A, g, r, method="sum", **kw):
     return lhaf_sum(A2, g2, ps, **kw)
 
 
+def lhafmix(A, g, n, method="sum", **kw):
+    """Mixed-state lhafmix(A, g, n) (App. B.2): A is 2M x 2M, row i paired
+    with row M+i, n_i times.  method 'sum': the paper's sum over z_i in
+    [0, n_i] with that pairing (kw: mode, prec, ...); 'explicit': the
+    definition on the matrix with rows i and M+i repeated n_i times."""
+    n = np.asarray(n, dtype=np.int64)
+    M = len(n)
+    if method == "explicit":
+        return lhaf_repeated(A, g, np.concatenate([n, n]), method="explicit", **kw)
+    keep = np.nonzero(n > 0)[0]
+    u = keep.astype(np.int32)
+    w = (keep + M).astype(np.int32)
+    return lhaf_sum(np.asarray(A, dtype=np.complex128), np.asarray(g, dtype=np.complex128),
+                    (u, w, n[keep].astype(np.int32)), **kw)
+
+
 def lhaf_chain_outputs(A, g, r, mode_b, n_cut, method="explicit", **kw):
     """Outputs of one chain-rule step by their definition (App. B.5): lhaf of
     the pattern r with mode_b set to k photons, for k = 0..n_cut."""

@@ -106,6 +106,25 @@ def lhaf_batched_workspace(idx_off, r=None, **kw) -> int:
                                                ctypes.byref(o)))
 
 
+def lhaf_mixed(A, gamma, n, *, sum="fds", acc="dd", term_begin=0, term_end=-1, scaled=True,
+               schedule=-1, return_error=False, workspace=None):
+    """Mixed-state lhafmix(A, gamma, n): A (2M, 2M), gamma (2M,), n host photon
+    numbers (M,); row i paired with row M+i, n_i times."""
+    A = _dev_c128(A, "A")
+    gamma = _dev_c128(gamma, "gamma")
+    nn = np.ascontiguousarray(np.asarray(n), dtype=np.int32)
+    M = len(nn)
+    if A.dim() != 2 or A.shape != (2 * M, 2 * M) or gamma.shape != (2 * M,):
+        raise ValueError("A (2M,2M) and gamma (2M,) required for M photon numbers")
+    out = torch.empty((), dtype=torch.complex128, device=A.device)
+    err = torch.empty((), dtype=torch.float64, device=A.device)
+    o = Bn.make_opts(sum, acc, term_begin, term_end, scaled, schedule, workspace)
+    with torch.cuda.device(A.device):
+        Bn.check(Bn.lib().lhaf_mixed(_p(A), 2 * M, _p(gamma), Bn.host_ptr(nn), M, _p(out), _p(err),
+                                     ctypes.byref(o), _stream_ptr(A.device)))
+    return (out, err) if return_error else out
+
+
 def lhaf_chain(A, gamma, r, mode_b: int, n_cut: int, *, acc="dd", schedule=-1,
                return_error=False, workspace=None):
     """One chain-rule step: out[k] = lhaf of the pattern r with mode_b at k

@@ -783,6 +783,49 @@ static lh_status backward_impl(int32_t B, const lh_c128* A_base, int64_t lda, in
   return LH_OK;
 }
 
+lh_status lhaf_mixed(const lh_c128* A, int64_t lda, const lh_c128* gamma, const int32_t* n,
+                     int32_t M, lh_c128* out, double* err_est, const lh_opts* opts, void* stream) {
+  lh_opts o;
+  lh_status s = validate_opts(opts, o);
+  if (s != LH_OK) return s;
+  if (M < 0 || !out || (M > 0 && !n)) return LH_EINVAL;
+  int64_t tot = 0;
+  for (int i = 0; i < M; ++i) {
+    if (n[i] < 0) return LH_EINVAL;
+    tot += n[i];
+  }
+  if (2 * tot > kMaxN || 2 * (int64_t)M > kMaxRows) return LH_ESIZE;
+  if (M > 0 && (!A || !gamma || lda < 2 * (int64_t)M)) return LH_EINVAL;
+  int dev = 0;
+  s = ensure_device(dev);
+  if (s != LH_OK) return s;
+  if (tot == 0) {
+    hipLaunchKernelGGL(fill_one_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, out, o.out_lo,
+                       err_est, 1);
+    return hipGetLastError() == hipSuccess ? LH_OK : LH_EHIP;
+  }
+  std::vector<ProblemIn> pin(1);
+  pin[0].plan = plan_mixed(n, M);
+  pin[0].a_off = pin[0].g_off = pin[0].i_off = 0;
+  Plan pl;
+  s = build_plan(pin, o, dev, pl, false);
+  if (s != LH_OK) return s;
+  if (o.saved) {
+    if (o.term_begin != 0 || o.term_end != -1) return LH_EUNSUPPORTED;
+    if (o.saved_count < pl.saved_need) return LH_ENOMEM;
+  }
+  void* ws = o.workspace;
+  std::unique_lock<std::mutex> lk(g_mu, std::defer_lock);
+  if (!ws) {
+    lk.lock();
+    s = get_scratch(dev, pl.lay.total, &ws);
+    if (s != LH_OK) return s;
+  } else if (o.ws_bytes < pl.lay.total) {
+    return LH_ENOMEM;
+  }
+  return run_forward(pl, A, lda, gamma, nullptr, out, err_est, o, ws, (hipStream_t)stream, dev);
+}
+
 lh_status lhaf_chain(const lh_c128* A, int64_t lda, const lh_c128* gamma, const int32_t* r,
                      int32_t M, int32_t mode_b, int32_t n_cut, lh_c128* out, double* err_est,
                      const lh_opts* opts, void* stream) {

@@ -67,6 +67,8 @@ struct PairPlan {
 PairPlan plan_plain(int N);
 // repeated problem: greedy matching on multiplicities r (App. B.3)
 PairPlan plan_repeated(const int32_t* r, int M);
+// mixed-state form (App. B.2): 2M rows, row i paired with row M + i, n_i times
+PairPlan plan_mixed(const int32_t* n, int M);
 // fill a Prob (without offsets / items) for `mode` over [t0, t1)
 bool fill_prob(const PairPlan& pp, int mode, int64_t t0, int64_t t1, bool scaled, Prob* out);
 int64_t term_count(const PairPlan& pp, int mode, int* hp_out);

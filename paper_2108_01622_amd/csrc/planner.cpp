@@ -90,6 +90,28 @@ PairPlan plan_repeated(const int32_t* r, int M) {
   return pp;
 }
 
+PairPlan plan_mixed(const int32_t* n, int M) {
+  PairPlan pp;
+  pp.rows = 2 * M;
+  pp.N = 0;
+  std::vector<int> u, w;
+  for (int i = 0; i < M; ++i)
+    if (n[i] > 0) {
+      u.push_back(i);
+      w.push_back(M + i);
+      pp.eta.push_back(n[i]);
+      pp.N += 2 * n[i];
+    }
+  pp.H = (int)u.size();
+  pp.n = pp.N / 2;
+  pp.pos.resize(2 * pp.H);
+  for (int p = 0; p < pp.H; ++p) {
+    pp.pos[p] = u[p];
+    pp.pos[pp.H + p] = w[p];
+  }
+  return pp;
+}
+
 int64_t term_count(const PairPlan& pp, int mode, int* hp_out) {
   int hp = -1;
   if (mode == 1) {

@@ -150,6 +150,26 @@ def chain4096(count: int = 4096):
                 idx_off=offs, sizes=sizes.astype(np.int32))
 
 
+def mixed_state(M: int, instance: int = 0):
+    """Stand-in for a mixed Gaussian state's 2M x 2M loop-hafnian matrix: the
+    block form [[B, C], [C^T, conj(B)]] with B = U diag(t) U^T (squeezing,
+    t_i = tanh r_i, r ~ U[0.5, 1.5] scaled by 0.6) and C = U diag(c) U^dagger
+    Hermitian PSD (thermal part, c ~ U[0, 0.3]), U Haar; gamma = (beta,
+    conj(beta)) with beta ~ CN(0, 0.1).  Photon numbers n: M modes, each 0..3
+    drawn with probabilities (0.2, 0.45, 0.25, 0.1)."""
+    rng = rng_for(6, instance)
+    U = haar_unitary(M, rng)
+    t = 0.6 * np.tanh(rng.uniform(0.5, 1.5, size=M))
+    c = rng.uniform(0.0, 0.3, size=M)
+    Bm = (U * t) @ U.T
+    Cm = (U * c) @ U.conj().T
+    A = np.block([[Bm, Cm], [Cm.T, Bm.conj()]]).astype(np.complex128)
+    beta = complex_normal(rng, M, 0.1)
+    gamma = np.concatenate([beta, beta.conj()]).astype(np.complex128)
+    n = rng.choice(4, size=M, p=[0.2, 0.45, 0.25, 0.1]).astype(np.int32)
+    return A, gamma, n
+
+
 # --------------------------------------------------------------------------
 # workload 4: precision stress
 def dense_symmetric(n: int, rng: np.random.Generator, var: float):

@@ -338,3 +338,19 @@ def test_gamma_outputs_closed_forms(orc):
     for k, g in enumerate(G):
         want = g[0] * g[1] * g[2] + A[0, 1] * g[2] + A[0, 2] * g[1] + A[1, 2] * g[0]
         assert abs(out[k] - want) <= 1e-13 * abs(want)
+
+
+@pytest.mark.parametrize("n", [[1, 0, 2], [2, 2, 1], [3, 0, 0], [1, 1, 1, 1]])
+@pytest.mark.parametrize("mode", ["et", "fds"])
+def test_lhafmix_sum_matches_definition(orc, n, mode):
+    """The paper's lhafmix sum (pairs (i, M+i) repeated n_i times, App. B.2)
+    against the definition on the explicitly repeated 2M x 2M matrix."""
+    from paper_2108_01622_amd import inputs as I
+    M = len(n)
+    A, g, _ = I.mixed_state(M, 7)
+    want = orc.lhafmix(A, g, n, method="explicit", prec="f128")
+    got = orc.lhafmix(A, g, n, mode=mode, prec="f128")
+    assert abs(got - want) <= 1e-12 * abs(want)
+    # the greedy pairing of the same pattern gives the same value
+    other = orc.lhaf_repeated(A, g, np.concatenate([n, n]), method="sum", mode=mode, prec="f128")
+    assert abs(other - want) <= 1e-12 * abs(want)
