@@ -356,6 +356,19 @@ def main():
                                   "seconds": t_mix, "greedy_repeated_seconds": t_greedy,
                                   "terms": Tm,
                                   "terms_per_s": Tm / t_mix}
+        # real non-negative N = 40 lhaf (real FP64 kernel) against the complex
+        # kernels on the same entries
+        rng = np.random.Generator(np.random.PCG64(4041))
+        Ar = rng.uniform(0.0, 0.2, size=(N, N))
+        Ar = 0.5 * (Ar + Ar.T)
+        gr = rng.uniform(0.0, 1.0, size=N)
+        Art, grt = torch.as_tensor(Ar, device=dev), torch.as_tensor(gr, device=dev)
+        t_real = timed(lambda: api.lhaf_real(Art, grt))
+        t_cplx = timed(lambda: api.lhaf(Art.to(torch.complex128), grt.to(torch.complex128)))
+        res["real_nonneg_n40"] = {"workload": "one real non-negative N=40 lhaf, FDS dd",
+                                  "seconds": t_real, "complex_kernel_seconds": t_cplx,
+                                  "terms_per_s": terms_per_problem / t_real,
+                                  "speedup_vs_complex": t_cplx / t_real}
         print("[bench] multi-output done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(A_np[0], g_np[0])

@@ -160,6 +160,15 @@ lh_status lhaf_batched(int32_t B, const lh_c128* A_base, int64_t lda, int64_t st
 lh_status lhaf_mixed(const lh_c128* A, int64_t lda, const lh_c128* gamma, const int32_t* n,
                      int32_t M, lh_c128* out, double* err_est, const lh_opts* opts, void* stream);
 
+/* lhaf of a real symmetric matrix with real loop weights (e.g. the
+ * non-negative matrices of the MIS independence proposal, App. C), in real
+ * FP64 arithmetic: the same sums, enumeration and coefficients as lhaf /
+ * lhaf_repeated (r: HOST multiplicities or NULL = plain M x M).  A, gamma:
+ * device doubles (lda >= M); out, err_est (nullable): device, one double.
+ * opts->saved and opts->out_lo are not supported (LH_EUNSUPPORTED). */
+lh_status lhaf_real(const double* A, int64_t lda, const double* gamma, const int32_t* r,
+                    int32_t M, double* out, double* err_est, const lh_opts* opts, void* stream);
+
 /* One chain-rule step (App. B.5, batching over the batched mode's outcome):
  * out[k] = lhaf(A_{r(k)}, gamma_{r(k)}), k = 0..n_cut, where r(k) is the host
  * pattern r (M entries, r[mode_b] must be 0) with mode_b set to k photons.

@@ -106,6 +106,27 @@ def lhaf_batched_workspace(idx_off, r=None, **kw) -> int:
                                                ctypes.byref(o)))
 
 
+def lhaf_real(A, gamma=None, r=None, *, sum="fds", acc="dd", term_begin=0, term_end=-1,
+              scaled=True, schedule=-1, return_error=False, workspace=None):
+    """Loop hafnian of a real symmetric matrix with real loop weights, in real
+    FP64 (float64 device tensors; gamma=None takes diag(A))."""
+    if not isinstance(A, torch.Tensor) or A.device.type != "cuda":
+        raise ValueError("A must be a ROCm device tensor")
+    A = A.to(torch.float64).contiguous()
+    M = A.shape[0]
+    if A.dim() != 2 or A.shape[1] != M:
+        raise ValueError("A must be square")
+    gamma = torch.diagonal(A).contiguous() if gamma is None else gamma.to(torch.float64).contiguous()
+    out = torch.empty((), dtype=torch.float64, device=A.device)
+    err = torch.empty((), dtype=torch.float64, device=A.device)
+    rr = None if r is None else np.ascontiguousarray(np.asarray(r), dtype=np.int32)
+    o = Bn.make_opts(sum, acc, term_begin, term_end, scaled, schedule, workspace)
+    with torch.cuda.device(A.device):
+        Bn.check(Bn.lib().lhaf_real(_p(A), M, _p(gamma), Bn.host_ptr(rr), M, _p(out), _p(err),
+                                    ctypes.byref(o), _stream_ptr(A.device)))
+    return (out, err) if return_error else out
+
+
 def lhaf_mixed(A, gamma, n, *, sum="fds", acc="dd", term_begin=0, term_end=-1, scaled=True,
                schedule=-1, return_error=False, workspace=None):
     """Mixed-state lhafmix(A, gamma, n): A (2M, 2M), gamma (2M,), n host photon

@@ -19,6 +19,7 @@
 #include "lhaf_forward.hip"
 #include "lhaf_backward.hip"
 #include "lhaf_multi.hip"
+#include "lhaf_real.hip"
 
 namespace lh {
 
@@ -824,6 +825,84 @@ lh_status lhaf_mixed(const lh_c128* A, int64_t lda, const lh_c128* gamma, const 
     return LH_ENOMEM;
   }
   return run_forward(pl, A, lda, gamma, nullptr, out, err_est, o, ws, (hipStream_t)stream, dev);
+}
+
+lh_status lhaf_real(const double* A, int64_t lda, const double* gamma, const int32_t* r,
+                    int32_t M, double* out, double* err_est, const lh_opts* opts, void* stream) {
+  lh_opts o;
+  lh_status s = validate_opts(opts, o);
+  if (s != LH_OK) return s;
+  if (o.saved || o.out_lo) return LH_EUNSUPPORTED;
+  if (M < 0 || !out) return LH_EINVAL;
+  PairPlan pp;
+  if (r) {
+    int64_t tot = 0;
+    for (int i = 0; i < M; ++i) {
+      if (r[i] < 0) return LH_EINVAL;
+      tot += r[i];
+    }
+    if (tot > kMaxN || M > kMaxRows) return LH_ESIZE;
+    pp = plan_repeated(r, M);
+  } else {
+    if (M > kMaxN) return LH_ESIZE;
+    pp = plan_plain(M);
+  }
+  if (M > 0 && (!A || !gamma || lda < M)) return LH_EINVAL;
+  int dev = 0;
+  s = ensure_device(dev);
+  if (s != LH_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<ProblemIn> pin(1);
+  pin[0].plan = pp;
+  pin[0].a_off = pin[0].g_off = pin[0].i_off = 0;
+  Plan pl;
+  s = build_plan(pin, o, dev, pl, false);
+  if (s != LH_OK) return s;
+  void* ws = o.workspace;
+  std::unique_lock<std::mutex> lk(g_mu, std::defer_lock);
+  if (!ws) {
+    lk.lock();
+    s = get_scratch(dev, pl.lay.total, &ws);
+    if (s != LH_OK) return s;
+  } else if (o.ws_bytes < pl.lay.total) {
+    return LH_ENOMEM;
+  }
+  char* base = static_cast<char*>(ws);
+  s = upload_plan(pl, base, st, dev);
+  if (s != LH_OK) return s;
+  hipLaunchKernelGGL(real::pack_kernel, dim3(1), dim3(256), 0, st,
+                     reinterpret_cast<const Prob*>(base + pl.lay.probs), A, lda, gamma,
+                     reinterpret_cast<double*>(base + pl.lay.cdata),
+                     reinterpret_cast<int*>(base + pl.lay.counter));
+  if (hipGetLastError() != hipSuccess) return LH_EHIP;
+  const int acc_dd = o.acc == LH_ACC_DD ? 1 : 0;
+  if (!pl.items.empty()) {
+    const int nmax = std::max(pl.nmax, 1);
+    const size_t lds = real::lds_bytes(nmax);
+#define LH_RLAUNCH(BB)                                                                        \
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(real::real_kernel<BB>), dim3(pl.grid), dim3(64), lds, st, \
+                     reinterpret_cast<const Prob*>(base + pl.lay.probs),                      \
+                     reinterpret_cast<const Item*>(base + pl.lay.items), (int)pl.items.size(), \
+                     reinterpret_cast<int*>(base + pl.lay.counter),                           \
+                     reinterpret_cast<const double*>(base + pl.lay.cdata),                    \
+                     reinterpret_cast<Partial*>(base + pl.lay.parts), acc_dd, nmax)
+    switch (pl.bmax) {
+      case 1: LH_RLAUNCH(1); break;
+      case 2: LH_RLAUNCH(2); break;
+      case 3: LH_RLAUNCH(3); break;
+      case 4: LH_RLAUNCH(4); break;
+      case 5: LH_RLAUNCH(5); break;
+      case 6: LH_RLAUNCH(6); break;
+      case 7: LH_RLAUNCH(7); break;
+      default: LH_RLAUNCH(8); break;
+    }
+#undef LH_RLAUNCH
+    if (hipGetLastError() != hipSuccess) return LH_EHIP;
+  }
+  hipLaunchKernelGGL(real::finalize_kernel, dim3(1), dim3(64), 0, st,
+                     reinterpret_cast<const Prob*>(base + pl.lay.probs),
+                     reinterpret_cast<const Partial*>(base + pl.lay.parts), out, err_est, acc_dd);
+  return hipGetLastError() == hipSuccess ? LH_OK : LH_EHIP;
 }
 
 lh_status lhaf_chain(const lh_c128* A, int64_t lda, const lh_c128* gamma, const int32_t* r,

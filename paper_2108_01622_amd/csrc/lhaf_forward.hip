@@ -55,7 +55,13 @@ __device__ inline LdsView carve(char* base, int nmax) {
   return L;
 }
 
-__device__ __forceinline__ int ring_slot(int k, int NR) { return (k + 1) % NR; }
+// Slot of T_k in the ring of NR = nmax + 2 polynomials.  k + 1 < 2 NR
+// (k < m = 2H <= 2n <= 2 nmax), so one conditional subtraction replaces the
+// integer remainder.
+__device__ __forceinline__ int ring_slot(int k, int NR) {
+  const int s = k + 1;
+  return s >= NR ? s - NR : s;
+}
 
 // -------------------------------------------------------------------------
 // One Householder step of the Hessenberg reduction: column j (= 8*kb + jj)
