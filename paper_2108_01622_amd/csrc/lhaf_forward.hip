@@ -564,7 +564,7 @@ __global__ void pack_kernel(const Prob* __restrict__ probs, const int64_t* __res
 
 // resident wavefronts per SIMD the register allocation aims for, by tile
 #ifndef LH_FWD_WAVES
-#define LH_FWD_WAVES(bmax) ((bmax) <= 2 ? 4 : ((bmax) <= 3 ? 3 : ((bmax) <= 5 ? 2 : 1)))
+#define LH_FWD_WAVES(bmax) ((bmax) <= 3 ? 4 : ((bmax) <= 4 ? 3 : ((bmax) <= 6 ? 2 : 1)))
 #endif
 
 template <int BMAX>
