@@ -1,0 +1,62 @@
+"""Host logic of the measurement tooling (no GPU): rocprofv3 counter files are
+turned into HBM bytes with the copy-kernel factors, recorded per kernel with
+the hash of the kernel sources, and reported only for those sources; the
+benchmark's Paterson-Stockmeyer product count."""
+import csv
+import importlib
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def write_counters(path, counter, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
+        for d, name, grid, val in rows:
+            w.writerow([d, name, grid, counter, val])
+
+
+@pytest.fixture
+def prof(tmp_path, monkeypatch):
+    from paper_2108_01622_amd import profiling
+    monkeypatch.setattr(profiling, "TRAFFIC_JSON", str(tmp_path / "traffic.json"))
+    return profiling
+
+
+def test_copy_factor_scaling_and_hash_gate(prof, tmp_path, monkeypatch):
+    kib = 1 << 20  # 1 GiB copy in KiB
+    fetch = tmp_path / "f.csv"
+    write = tmp_path / "w.csv"
+    kname = "void lh::backward_kernel<5>(lh::Prob const*, int)"
+    # the counter reads half of the copied bytes on FETCH, all of them on WRITE
+    write_counters(fetch, "FETCH_SIZE", [(1, "__amd_rocclr_copyBuffer", 512, kib / 2),
+                                         (2, kname, 64, 1000.0)])
+    write_counters(write, "WRITE_SIZE", [(1, "__amd_rocclr_copyBuffer", 512, kib),
+                                         (2, kname, 64, 300.0)])
+    md = prof.traffic_md(str(fetch), str(write), "backward_kernel<5>", 10, 1 << 30, "cmd", "t")
+    assert "factor 2.0000" in md and "factor 1.0000" in md
+    got = prof.stored_traffic("backward_kernel<5>", 10)
+    assert got == pytest.approx(1000 * 1024 * 2.0 + 300 * 1024 * 1.0)
+    assert prof.stored_traffic("forward_kernel<5>", 10) is None
+    # other kernel sources: the stored counters no longer apply
+    monkeypatch.setattr(prof, "kernel_source_hash", lambda: "different")
+    assert prof.stored_traffic("backward_kernel<5>", 10) is None
+
+
+def test_missing_copy_reference_is_an_error(prof, tmp_path):
+    fetch = tmp_path / "f.csv"
+    write_counters(fetch, "FETCH_SIZE", [(1, "lh::forward_kernel<5>(x)", 64, 5.0)])
+    with pytest.raises(SystemExit):
+        prof.traffic_md(str(fetch), str(fetch), "forward_kernel<5>", 1, 1 << 30, "c", "t")
+
+
+def test_paterson_stockmeyer_products():
+    sys.path.insert(0, ROOT)
+    bench = importlib.import_module("bench")
+    # s = ceil(sqrt n) powers W^2..W^s, then ceil(n/s) - 1 Horner steps
+    assert [bench.ps_products(n) for n in (1, 2, 4, 5, 9, 20, 26, 32)] == [0, 1, 2, 3, 4, 7, 9, 10]
+    assert bench.canonical_flops(40, 20) == pytest.approx(40 / 3 * 40 ** 3 + 8 * 20 * 1600)
