@@ -104,8 +104,9 @@ def main():
                          "the forward's coefficient store")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(the term sum shards by term ranges across GPUs, see DESIGN.md)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (across GPUs "
+                                   "the term sum shards by term ranges: each GPU evaluates its "
+                                   "term_begin/term_end share unscaled and the partial sums are added)"}))
         sys.exit(2)
 
     import torch
