@@ -15,11 +15,16 @@
 #include "lhaf.h"
 #include "lhaf_device.h"
 #include "lhaf_internal.h"
-// kernels (one translation unit with the launches)
+// Kernel sources: this unit compiles only the small non-templated kernels
+// (pack, finalize, reductions, scatters); the persistent kernels are
+// instantiated per tile in their own units (lhaf_tile.hip) and reached
+// through the launchers of lhaf_launch.h.
+#define LH_COMMON_KERNELS
 #include "lhaf_forward.hip"
 #include "lhaf_backward.hip"
 #include "lhaf_multi.hip"
 #include "lhaf_real.hip"
+#include "lhaf_launch.h"
 
 namespace lh {
 
@@ -27,7 +32,7 @@ namespace {
 
 std::mutex g_mu;
 struct DevState {
-  bool binom_ready = false;
+  bool binom_ready = false;  // device attributes read
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
   int cus = 0;
@@ -39,18 +44,6 @@ lh_status ensure_device(int& dev) {
   if (dev < 0 || dev >= 64) return LH_EHIP;
   DevState& S = g_dev[dev];
   if (!S.binom_ready) {
-    double tab[33][33];
-    for (int a = 0; a < 33; ++a)
-      for (int b = 0; b < 33; ++b) {
-        if (b > a) {
-          tab[a][b] = 0.0;
-          continue;
-        }
-        double r = 1.0;
-        for (int k = 1; k <= b; ++k) r = r * (a - b + k) / k;
-        tab[a][b] = std::round(r);
-      }
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_binom), tab, sizeof(tab)) != hipSuccess) return LH_EHIP;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return LH_EHIP;
@@ -169,20 +162,17 @@ struct Plan {
 // wavefronts of one kernel instance resident per CU (occupancy query)
 int resident_per_cu(bool bwd, int bmax, int nmax) {
   const size_t lds = bwd ? bwd_lds_bytes(bmax, std::max(nmax, 1)) : lds_bytes_for(std::max(nmax, 1));
-  const void* fn = nullptr;
+  int blocks = 0;
   switch (bmax) {
-#define LH_FN(BB)                                                                      \
-  case BB:                                                                             \
-    fn = bwd ? reinterpret_cast<const void*>(&backward_kernel<BB>)                     \
-             : reinterpret_cast<const void*>(&forward_kernel<BB>);                     \
+#define LH_FN(BB)                                                      \
+  case BB:                                                             \
+    blocks = bwd ? resident_backward<BB>(lds) : resident_forward<BB>(lds); \
     break;
     LH_FN(1) LH_FN(2) LH_FN(3) LH_FN(4) LH_FN(5) LH_FN(6) LH_FN(7)
     default: LH_FN(8)
 #undef LH_FN
   }
-  int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, 64, lds) != hipSuccess || blocks < 1)
-    blocks = 4;
+  if (blocks < 1) blocks = 4;
   return blocks;
 }
 
@@ -332,17 +322,18 @@ using namespace lh;
 
 namespace lh {
 
-template <int BMAX>
-static hipError_t launch_fwd(const Plan& pl, char* base, int acc_dd, cd* saved, hipStream_t st) {
-  const size_t lds = lds_bytes_for(std::max(pl.nmax, 1));
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(forward_kernel<BMAX>), dim3(pl.grid), dim3(64), lds, st,
-                     reinterpret_cast<const Prob*>(base + pl.lay.probs),
-                     reinterpret_cast<const Item*>(base + pl.lay.items), (int)pl.items.size(),
-                     reinterpret_cast<int*>(base + pl.lay.counter),
-                     reinterpret_cast<const cd*>(base + pl.lay.cdata),
-                     reinterpret_cast<Partial*>(base + pl.lay.parts), acc_dd, std::max(pl.nmax, 1),
-                     saved);
-  return hipGetLastError();
+// Launch shape and plan tables of a persistent kernel over plan `pl`.
+static PersistArgs persist_args(const Plan& pl, char* base, size_t lds, hipStream_t st) {
+  PersistArgs a;
+  a.probs = reinterpret_cast<const Prob*>(base + pl.lay.probs);
+  a.items = reinterpret_cast<const Item*>(base + pl.lay.items);
+  a.n_items = (int)pl.items.size();
+  a.counter = reinterpret_cast<int*>(base + pl.lay.counter);
+  a.nmax = std::max(pl.nmax, 1);
+  a.grid = pl.grid;
+  a.lds = lds;
+  a.stream = st;
+  return a;
 }
 
 // Copy the host plan (problem table, item list, offsets) into the workspace.
@@ -369,16 +360,16 @@ lh_status run_forward(Plan& pl, const lh_c128* A, int64_t lda, const lh_c128* g,
   const int acc_dd = o.acc == LH_ACC_DD ? 1 : 0;
   cd* sv = reinterpret_cast<cd*>(o.saved);
   if (!pl.items.empty()) {
+    const PersistArgs pa = persist_args(pl, base, lds_bytes_for(std::max(pl.nmax, 1)), st);
+    const cd* wsc = reinterpret_cast<const cd*>(base + pl.lay.cdata);
+    Partial* parts = reinterpret_cast<Partial*>(base + pl.lay.parts);
     hipError_t e;
     switch (pl.bmax) {
-      case 1: e = launch_fwd<1>(pl, base, acc_dd, sv, st); break;
-      case 2: e = launch_fwd<2>(pl, base, acc_dd, sv, st); break;
-      case 3: e = launch_fwd<3>(pl, base, acc_dd, sv, st); break;
-      case 4: e = launch_fwd<4>(pl, base, acc_dd, sv, st); break;
-      case 5: e = launch_fwd<5>(pl, base, acc_dd, sv, st); break;
-      case 6: e = launch_fwd<6>(pl, base, acc_dd, sv, st); break;
-      case 7: e = launch_fwd<7>(pl, base, acc_dd, sv, st); break;
-      default: e = launch_fwd<8>(pl, base, acc_dd, sv, st); break;
+#define LH_FCASE(BB) \
+  case BB: e = launch_forward<BB>(pa, wsc, parts, acc_dd, sv); break;
+      LH_FCASE(1) LH_FCASE(2) LH_FCASE(3) LH_FCASE(4) LH_FCASE(5) LH_FCASE(6) LH_FCASE(7)
+      default: LH_FCASE(8)
+#undef LH_FCASE
     }
     if (e != hipSuccess) return LH_EHIP;
   }
@@ -658,19 +649,12 @@ static lh_status multi_impl(const PairPlan& plan, const lh_c128* A, int64_t lda,
   if (!pl.items.empty()) {
     const int nmax = std::max(pl.nmax, 1);
     const size_t lds = multi_lds_bytes(nmax, ma.mode, ma.nout);
-#define LH_MLAUNCH(BB)                                                                         \
-  if (ma.mode == 1)                                                                            \
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(multi_kernel<BB, 1>), dim3(pl.grid), dim3(64), lds, st, \
-                       reinterpret_cast<const Prob*>(base + pl.lay.probs),                     \
-                       reinterpret_cast<const Item*>(base + pl.lay.items), (int)pl.items.size(), \
-                       reinterpret_cast<int*>(base + pl.lay.counter),                          \
-                       reinterpret_cast<const cd*>(base + pl.lay.cdata), parts, acc_dd, nmax, ma); \
-  else                                                                                         \
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(multi_kernel<BB, 0>), dim3(pl.grid), dim3(64), lds, st,   \
-                     reinterpret_cast<const Prob*>(base + pl.lay.probs),                       \
-                     reinterpret_cast<const Item*>(base + pl.lay.items), (int)pl.items.size(), \
-                     reinterpret_cast<int*>(base + pl.lay.counter),                            \
-                     reinterpret_cast<const cd*>(base + pl.lay.cdata), parts, acc_dd, nmax, ma)
+    const PersistArgs pa = persist_args(pl, base, lds, st);
+    const cd* wsc = reinterpret_cast<const cd*>(base + pl.lay.cdata);
+    hipError_t e;
+#define LH_MLAUNCH(BB)                                            \
+  e = ma.mode == 1 ? launch_multi<BB, 1>(pa, wsc, parts, acc_dd, ma) \
+                   : launch_multi<BB, 0>(pa, wsc, parts, acc_dd, ma)
     switch (pl.bmax) {
       case 1: LH_MLAUNCH(1); break;
       case 2: LH_MLAUNCH(2); break;
@@ -682,6 +666,7 @@ static lh_status multi_impl(const PairPlan& plan, const lh_c128* A, int64_t lda,
       default: LH_MLAUNCH(8); break;
     }
 #undef LH_MLAUNCH
+    if (e != hipSuccess) return LH_EHIP;
     if (hipGetLastError() != hipSuccess) return LH_EHIP;
   }
   hipLaunchKernelGGL(finalize_multi_kernel, dim3(1), dim3(64), 0, st,
@@ -746,24 +731,18 @@ static lh_status backward_impl(int32_t B, const lh_c128* A_base, int64_t lda, in
   cd* scratch = reinterpret_cast<cd*>(base + off_s);
   if (!pl.items.empty()) {
     const size_t lds = bwd_lds_bytes(pl.bmax, std::max(pl.nmax, 1));
-#define LH_BLAUNCH(BB)                                                                          \
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(backward_kernel<BB>), dim3(pl.grid), dim3(64), lds, st,    \
-                     reinterpret_cast<const Prob*>(base + pl.lay.probs),                        \
-                     reinterpret_cast<const Item*>(base + pl.lay.items), (int)pl.items.size(),  \
-                     reinterpret_cast<int*>(base + pl.lay.counter),                             \
-                     reinterpret_cast<const cd*>(base + pl.lay.cdata), gsl, scratch,            \
-                     std::max(pl.nmax, 1), reinterpret_cast<const cd*>(o.saved))
+    const PersistArgs pa = persist_args(pl, base, lds, st);
+    const cd* wsc = reinterpret_cast<const cd*>(base + pl.lay.cdata);
+    const cd* sv = reinterpret_cast<const cd*>(o.saved);
+    hipError_t e;
     switch (pl.bmax) {
-      case 1: LH_BLAUNCH(1); break;
-      case 2: LH_BLAUNCH(2); break;
-      case 3: LH_BLAUNCH(3); break;
-      case 4: LH_BLAUNCH(4); break;
-      case 5: LH_BLAUNCH(5); break;
-      case 6: LH_BLAUNCH(6); break;
-      case 7: LH_BLAUNCH(7); break;
-      default: LH_BLAUNCH(8); break;
+#define LH_BCASE(BB) \
+  case BB: e = launch_backward<BB>(pa, wsc, gsl, scratch, sv); break;
+      LH_BCASE(1) LH_BCASE(2) LH_BCASE(3) LH_BCASE(4) LH_BCASE(5) LH_BCASE(6) LH_BCASE(7)
+      default: LH_BCASE(8)
+#undef LH_BCASE
     }
-#undef LH_BLAUNCH
+    if (e != hipSuccess) return LH_EHIP;
     if (hipGetLastError() != hipSuccess) return LH_EHIP;
   }
   hipLaunchKernelGGL(greduce_kernel, dim3(nprob), dim3(256), 0, st,
@@ -879,24 +858,18 @@ lh_status lhaf_real(const double* A, int64_t lda, const double* gamma, const int
   if (!pl.items.empty()) {
     const int nmax = std::max(pl.nmax, 1);
     const size_t lds = real::lds_bytes(nmax);
-#define LH_RLAUNCH(BB)                                                                        \
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(real::real_kernel<BB>), dim3(pl.grid), dim3(64), lds, st, \
-                     reinterpret_cast<const Prob*>(base + pl.lay.probs),                      \
-                     reinterpret_cast<const Item*>(base + pl.lay.items), (int)pl.items.size(), \
-                     reinterpret_cast<int*>(base + pl.lay.counter),                           \
-                     reinterpret_cast<const double*>(base + pl.lay.cdata),                    \
-                     reinterpret_cast<Partial*>(base + pl.lay.parts), acc_dd, nmax)
+    const PersistArgs pa = persist_args(pl, base, lds, st);
+    const double* wsr = reinterpret_cast<const double*>(base + pl.lay.cdata);
+    Partial* parts = reinterpret_cast<Partial*>(base + pl.lay.parts);
+    hipError_t e;
     switch (pl.bmax) {
-      case 1: LH_RLAUNCH(1); break;
-      case 2: LH_RLAUNCH(2); break;
-      case 3: LH_RLAUNCH(3); break;
-      case 4: LH_RLAUNCH(4); break;
-      case 5: LH_RLAUNCH(5); break;
-      case 6: LH_RLAUNCH(6); break;
-      case 7: LH_RLAUNCH(7); break;
-      default: LH_RLAUNCH(8); break;
+#define LH_RCASE(BB) \
+  case BB: e = launch_real<BB>(pa, wsr, parts, acc_dd); break;
+      LH_RCASE(1) LH_RCASE(2) LH_RCASE(3) LH_RCASE(4) LH_RCASE(5) LH_RCASE(6) LH_RCASE(7)
+      default: LH_RCASE(8)
+#undef LH_RCASE
     }
-#undef LH_RLAUNCH
+    if (e != hipSuccess) return LH_EHIP;
     if (hipGetLastError() != hipSuccess) return LH_EHIP;
   }
   hipLaunchKernelGGL(real::finalize_kernel, dim3(1), dim3(64), 0, st,

@@ -509,6 +509,7 @@ __global__ LH_BWD_ATTR void backward_kernel(const Prob* __restrict__ probs,
   }
 }
 
+#ifdef LH_COMMON_KERNELS
 // Sum the item gradients of each problem (in item order) into its first slot.
 __global__ void greduce_kernel(const Prob* __restrict__ probs, cd* __restrict__ gslots) {
   const Prob& P = probs[blockIdx.x];
@@ -643,5 +644,7 @@ __global__ void scatter_shared_kernel(const Prob* __restrict__ probs, int nprob,
   else
     dg[e - (int64_t)base_dim * base_dim] = r;
 }
+
+#endif  // LH_COMMON_KERNELS
 
 }  // namespace lh

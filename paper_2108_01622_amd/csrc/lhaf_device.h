@@ -5,6 +5,25 @@
 
 namespace lh {
 
+// Binomial coefficients C(a, b), 0 <= b <= a <= 32, exact in double (the
+// largest, C(32, 16), is below 2^30).  Built at compile time, so every
+// translation unit that includes this header has its own initialised copy.
+struct BinomTable {
+  double v[33][33];
+};
+constexpr BinomTable make_binom_table() {
+  BinomTable t{};
+  for (int a = 0; a <= 32; ++a) {
+    unsigned long long c = 1;  // C(a, b), built up along the row
+    for (int b = 0; b <= 32; ++b) {
+      t.v[a][b] = b <= a ? (double)c : 0.0;
+      if (b < a) c = c * (unsigned long long)(a - b) / (unsigned long long)(b + 1);
+    }
+  }
+  return t;
+}
+static __constant__ BinomTable c_binom = make_binom_table();
+
 struct cd {
   double r, i;
 };

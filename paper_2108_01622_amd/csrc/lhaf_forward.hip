@@ -23,8 +23,6 @@
 
 namespace lh {
 
-__constant__ double c_binom[33][33];
-
 // LDS layout of one wavefront (dynamic shared memory).
 struct LdsView {
   cd* wv;      // [65] Householder vector (by row)
@@ -292,11 +290,11 @@ __device__ __forceinline__ double term_weight(const TermIter& it, const Prob& P,
   double wl, fl;
   if (fds) {
     wl = (double)(it.eta_l - 2 * it.digit);
-    fl = ((it.digit & 1) ? -1.0 : 1.0) * c_binom[it.eta_l][it.digit];
+    fl = ((it.digit & 1) ? -1.0 : 1.0) * c_binom.v[it.eta_l][it.digit];
     if (lane == P.hp && 2 * it.digit != it.eta_l) fl *= 2.0;
   } else {
     wl = (double)it.digit;
-    fl = (((it.eta_l - it.digit) & 1) ? -1.0 : 1.0) * c_binom[it.eta_l][it.digit];
+    fl = (((it.eta_l - it.digit) & 1) ? -1.0 : 1.0) * c_binom.v[it.eta_l][it.digit];
   }
   if (lane >= P.H) {
     wl = 0.0;
@@ -508,6 +506,7 @@ __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const 
   }
 }
 
+#ifdef LH_COMMON_KERNELS
 // -------------------------------------------------------------------------
 // Pack the reduced matrix of every problem: Cp[i][c] = C[i][partner(c)] with
 // C[i][j] = sym(A)[mode(i)][mode(j)]; C's diagonal is kept only for repeated
@@ -562,6 +561,8 @@ __global__ void pack_kernel(const Prob* __restrict__ probs, const int64_t* __res
   if (b == 0 && threadIdx.x == 0) *counter = 0;
 }
 
+#endif  // LH_COMMON_KERNELS
+
 // resident wavefronts per SIMD the register allocation aims for, by tile
 #ifndef LH_FWD_WAVES
 #define LH_FWD_WAVES(bmax) ((bmax) <= 3 ? 4 : ((bmax) <= 4 ? 3 : ((bmax) <= 6 ? 2 : 1)))
@@ -609,6 +610,7 @@ __attribute__((amdgpu_waves_per_eu(LH_FWD_WAVES(BMAX), LH_FWD_WAVES(BMAX)))) voi
   }
 }
 
+#ifdef LH_COMMON_KERNELS
 // Sum the item partials of each problem in item order (double-double),
 // apply the FDS prefactor and write the result and an error estimate.
 __global__ void finalize_kernel(const Prob* __restrict__ probs, int nprob,
@@ -676,5 +678,7 @@ __global__ void fill_one_kernel(lh_c128* out, lh_c128* out_lo, double* err, int 
   }
   if (err) err[b] = 0.0;
 }
+
+#endif  // LH_COMMON_KERNELS
 
 }  // namespace lh

@@ -1,0 +1,51 @@
+// Host-side launchers of the persistent (register-tile templated) kernels.
+// Each instantiation lives in its own translation unit (lhaf_tile.hip built
+// once per kernel family and tile), so the library compiles in parallel; the
+// API layer only sees these declarations.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lhaf_device.h"
+#include "lhaf_internal.h"
+
+namespace lh {
+
+struct MultiArgs;  // lhaf_multi.hip
+
+// Arguments shared by every persistent launch: the plan tables in the
+// workspace, the work counter, the packed problems and the launch shape.
+struct PersistArgs {
+  const Prob* probs;
+  const Item* items;
+  int n_items;
+  int* counter;
+  int nmax;
+  int grid;
+  size_t lds;
+  hipStream_t stream;
+};
+
+// forward_kernel<B>: item partials (and the per-term coefficient store)
+template <int B>
+hipError_t launch_forward(const PersistArgs& a, const cd* ws, Partial* parts, int acc_dd,
+                          cd* saved);
+// backward_kernel<B>: item gradient slots; per-wavefront scratch
+template <int B>
+hipError_t launch_backward(const PersistArgs& a, const cd* ws, cd* gslots, cd* scratch,
+                           const cd* saved);
+// multi_kernel<B, MODE>: MODE 0 chain-rule outputs, 1 loop-weight vectors
+template <int B, int MODE>
+hipError_t launch_multi(const PersistArgs& a, const cd* ws, Partial* parts, int acc_dd,
+                        const MultiArgs& ma);
+// real::real_kernel<B>
+template <int B>
+hipError_t launch_real(const PersistArgs& a, const double* ws, Partial* parts, int acc_dd);
+
+// Resident workgroups per CU of one instance with `lds` bytes of dynamic LDS
+// (occupancy query of the runtime; 0 if the query fails).
+template <int B>
+int resident_forward(size_t lds);
+template <int B>
+int resident_backward(size_t lds);
+
+}  // namespace lh

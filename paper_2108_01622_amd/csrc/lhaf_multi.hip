@@ -111,12 +111,12 @@ __device__ __forceinline__ void run_item_multi(const Prob& P, const int64_t t0, 
       const int zbp = ma.pbp >= 0 ? __builtin_amdgcn_readlane(it.digit, ma.pbp) : 0;
       // binomial weights of the fixed pairs, parity of sum z
       const bool fixed = lane < H && lane != ma.pbb && lane != ma.pbp;
-      const double cf = prod_wave(fixed ? c_binom[it.eta_l][it.digit] : 1.0);
+      const double cf = prod_wave(fixed ? c_binom.v[it.eta_l][it.digit] : 1.0);
       const int zpar = __popcll(__ballot(lane < H && (it.digit & 1))) & 1;
       if (lane < ma.nout) {
         const int jk = lane >> 1, ok = lane & 1;
         const int nk = ma.nf + jk + ok;
-        const double cb = c_binom[jk][zbb] * c_binom[ok][zbp];
+        const double cb = c_binom.v[jk][zbb] * c_binom.v[ok][zbp];
         if (cb != 0.0 && nk >= 1) {
           cd e0 = czero(), e1 = czero();
           int i = 0;
@@ -182,6 +182,7 @@ __attribute__((amdgpu_waves_per_eu(LH_FWD_WAVES(BMAX), LH_FWD_WAVES(BMAX)))) voi
   }
 }
 
+#ifdef LH_COMMON_KERNELS
 // gamma mode: vg[g][i] = gamma_g[mode of vertex i] (1 for padding, 0 beyond m)
 __global__ void pack_gammas_kernel(const Prob* __restrict__ probs, const lh_c128* __restrict__ g,
                                    int64_t ldg, int G, cd* __restrict__ vg) {
@@ -236,5 +237,7 @@ __global__ void finalize_multi_kernel(const Prob* __restrict__ probs,
     err[o] = e;
   }
 }
+
+#endif  // LH_COMMON_KERNELS
 
 }  // namespace lh

@@ -369,6 +369,7 @@ __attribute__((amdgpu_waves_per_eu(LH_REAL_WAVES(BMAX), LH_REAL_WAVES(BMAX)))) v
   }
 }
 
+#ifdef LH_COMMON_KERNELS
 // reduced matrix and loop vector of one real problem (the rules of
 // pack_kernel), stored as doubles at twice the complex offset
 __global__ void pack_kernel(const Prob* __restrict__ probs, const double* __restrict__ A,
@@ -432,6 +433,8 @@ __global__ void finalize_kernel(const Prob* __restrict__ probs, const Partial* _
     *err = e;
   }
 }
+
+#endif  // LH_COMMON_KERNELS
 
 }  // namespace real
 }  // namespace lh

@@ -1,0 +1,94 @@
+// One register tile of one persistent-kernel family, as its own translation
+// unit.  Built once per (LH_FAMILY, LH_TILE):
+//   LH_FAMILY 0 forward_kernel<LH_TILE> (+ occupancy query)
+//   LH_FAMILY 1 backward_kernel<LH_TILE> (+ occupancy query)
+//   LH_FAMILY 2 multi_kernel<LH_TILE, 0 and 1>
+//   LH_FAMILY 3 real::real_kernel<LH_TILE>
+#include <hip/hip_runtime.h>
+
+#ifndef LH_TILE
+#error "LH_TILE (register tile 1..8) must be defined"
+#endif
+#ifndef LH_FAMILY
+#error "LH_FAMILY (0 forward, 1 backward, 2 multi, 3 real) must be defined"
+#endif
+
+#include "lhaf.h"
+#include "lhaf_device.h"
+#include "lhaf_internal.h"
+#include "lhaf_forward.hip"
+#if LH_FAMILY == 1
+#include "lhaf_backward.hip"
+#elif LH_FAMILY == 2
+#include "lhaf_multi.hip"
+#elif LH_FAMILY == 3
+#include "lhaf_real.hip"
+#endif
+#include "lhaf_launch.h"
+
+namespace lh {
+
+// Each unit defines the launcher templates of its family and instantiates
+// them for its tile only; the API unit sees the declarations of
+// lhaf_launch.h and links against these instantiations.
+#if LH_FAMILY == 0
+template <int B>
+hipError_t launch_forward(const PersistArgs& a, const cd* ws, Partial* parts, int acc_dd,
+                          cd* saved) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(forward_kernel<B>), dim3(a.grid), dim3(64), a.lds, a.stream,
+                     a.probs, a.items, a.n_items, a.counter, ws, parts, acc_dd, a.nmax, saved);
+  return hipGetLastError();
+}
+template <int B>
+int resident_forward(size_t lds) {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &blocks, reinterpret_cast<const void*>(&forward_kernel<B>), 64, lds) != hipSuccess)
+    return 0;
+  return blocks;
+}
+template hipError_t launch_forward<LH_TILE>(const PersistArgs&, const cd*, Partial*, int, cd*);
+template int resident_forward<LH_TILE>(size_t);
+#elif LH_FAMILY == 1
+template <int B>
+hipError_t launch_backward(const PersistArgs& a, const cd* ws, cd* gslots, cd* scratch,
+                           const cd* saved) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(backward_kernel<B>), dim3(a.grid), dim3(64), a.lds,
+                     a.stream, a.probs, a.items, a.n_items, a.counter, ws, gslots, scratch, a.nmax,
+                     saved);
+  return hipGetLastError();
+}
+template <int B>
+int resident_backward(size_t lds) {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &blocks, reinterpret_cast<const void*>(&backward_kernel<B>), 64, lds) != hipSuccess)
+    return 0;
+  return blocks;
+}
+template hipError_t launch_backward<LH_TILE>(const PersistArgs&, const cd*, cd*, cd*, const cd*);
+template int resident_backward<LH_TILE>(size_t);
+#elif LH_FAMILY == 2
+template <int B, int MODE>
+hipError_t launch_multi(const PersistArgs& a, const cd* ws, Partial* parts, int acc_dd,
+                        const MultiArgs& ma) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(multi_kernel<B, MODE>), dim3(a.grid), dim3(64), a.lds,
+                     a.stream, a.probs, a.items, a.n_items, a.counter, ws, parts, acc_dd, a.nmax,
+                     ma);
+  return hipGetLastError();
+}
+template hipError_t launch_multi<LH_TILE, 0>(const PersistArgs&, const cd*, Partial*, int,
+                                             const MultiArgs&);
+template hipError_t launch_multi<LH_TILE, 1>(const PersistArgs&, const cd*, Partial*, int,
+                                             const MultiArgs&);
+#elif LH_FAMILY == 3
+template <int B>
+hipError_t launch_real(const PersistArgs& a, const double* ws, Partial* parts, int acc_dd) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(real::real_kernel<B>), dim3(a.grid), dim3(64), a.lds,
+                     a.stream, a.probs, a.items, a.n_items, a.counter, ws, parts, acc_dd, a.nmax);
+  return hipGetLastError();
+}
+template hipError_t launch_real<LH_TILE>(const PersistArgs&, const double*, Partial*, int);
+#endif
+
+}  // namespace lh
