@@ -82,15 +82,30 @@ typedef struct {
                          results (out holds the high parts) */
   lh_c128* saved;     /* nullable device array of lhaf_saved_count() per-term
                          series coefficients shared by one lhaf_batched call and
-                         the lhaf_backward call on the same batch and sum mode:
-                         the forward writes a_k = e_{n-k}/2 (k = 1..n, e_j the
-                         lambda^j coefficient of exp(sum_k g_k lambda^k)) of
-                         every term, the backward reads them instead of
-                         repeating the Hessenberg reduction.  Problem b's block
-                         starts after the blocks of problems < b; term t's
-                         entries start at t*n_b inside it.  The forward needs the
-                         full term range.  The backward trusts the contents. */
+                         the lhaf_backward call on the same batch, sum mode and
+                         term range: the forward writes a_k = e_{n-k}/2
+                         (k = 1..n, e_j the lambda^j coefficient of
+                         exp(sum_k g_k lambda^k)) of every term of the range,
+                         the backward reads them instead of repeating the
+                         Hessenberg reduction.  Problem b's block starts after
+                         the blocks of problems < b; term t's entries start at
+                         (t - term_begin_b) * n_b inside it, term_begin_b being
+                         the range clipped to the problem.  The backward trusts
+                         the contents. */
   int64_t saved_count; /* entries available at saved */
+  lh_c128* grads;     /* nullable device array of lhaf_grads_count() entries:
+                         the per-problem reduced gradient of a batch (LD^2 + 64
+                         entries per problem, LD = 8 ceil(m/8)).  On
+                         lhaf_batched / lhaf / lhaf_repeated it selects the
+                         fused pass: one persistent launch evaluates every term
+                         once, adds c_t f_t into the values (out, err_est,
+                         opts->scaled honoured) and the term's adjoint into
+                         grads (with the FDS prefactor; a term range gives its
+                         share).  On lhaf_backward over the same batch it
+                         replaces the term pass: only the mapping to dA,
+                         dgamma with grad_out runs.  Nothing per term is kept.
+                         Not with saved, nor with the other entry points. */
+  int64_t grads_count; /* entries available at grads */
 } lh_opts;
 
 /* Term enumeration (identical for every entry point).  Pairs p = 0..H-1 with
@@ -196,8 +211,8 @@ lh_status lhaf_gammas(const lh_c128* A, int64_t lda, const lh_c128* gammas, int6
                       const lh_opts* opts, void* stream);
 
 /* Entries (lh_c128) of the per-term coefficient store of the batch for
- * opts->sum: sum over problems of terms x n.  Host only; a negative value is
- * -lh_status. */
+ * opts->sum and opts' term range: sum over problems of (terms in the range)
+ * x n.  Host only; a negative value is -lh_status. */
 int64_t lhaf_saved_count(int32_t B, const int64_t* idx_off, const int32_t* r, const lh_opts* opts);
 
 /* Gradients of the batch above (the paper has none; adjoint of the per-term
@@ -208,12 +223,24 @@ int64_t lhaf_saved_count(int32_t B, const int64_t* idx_off, const int32_t* r, co
  *   d lhaf / d A_ij = d lhaf / d A_ji = lhaf(A without rows/cols i,j) / 2  (i != j),
  *   d lhaf / d gamma_i = lhaf(A without row/col i),
  *   d lhaf / d A_ii = 0 for plain problems, C(r_i,2) lhaf(A_{r-2e_i}) repeated.
- * dA: device; if stride_A != 0, problem b writes dA + b*stride_A (lda); if
- * stride_A == 0, gradients of all problems are summed into one base-sized dA.
- * dgamma likewise with stride_g.  Both are overwritten (not accumulated).
+ * base_dim: rows of each matrix (1..4096; lda >= base_dim); every index list
+ * entry must be below it.  dA: device; if stride_A != 0, problem b writes the
+ * base_dim x base_dim block dA + b*stride_A (lda) and dgamma + b*stride_g
+ * (base_dim entries), rows no vertex maps to getting 0; if stride_A == 0,
+ * gradients of all problems are summed into one base-sized dA and dgamma.
+ * Both are overwritten (not accumulated).
+ * opts->term_begin / term_end select a term range of every problem: the
+ * result is that range's share of the gradient (FDS prefactor applied), so
+ * the results of disjoint ranges covering all terms add up to the full
+ * gradient (each term is independent, App. B.6).  opts->scaled is ignored.
+ * With opts->saved, the store must come from the forward over the same
+ * batch, sum mode and term range.
  * workspace: at least lhaf_backward_workspace(...) bytes. */
 size_t lhaf_backward_workspace(int32_t B, const int64_t* idx_off, const int32_t* r,
                                int32_t base_dim, const lh_opts* opts);
+/* Entries (lh_c128) of opts->grads for the batch (host only; negative:
+ * -lh_status). */
+int64_t lhaf_grads_count(int32_t B, const int64_t* idx_off, const int32_t* r);
 lh_status lhaf_backward(int32_t B, const lh_c128* A_base, int64_t lda, int64_t stride_A,
                         const lh_c128* gamma_base, int64_t stride_g, const int32_t* idx,
                         const int64_t* idx_off, const int32_t* r, const lh_c128* grad_out,

@@ -33,6 +33,8 @@ class LhOpts(ctypes.Structure):
         ("out_lo", ctypes.c_void_p),
         ("saved", ctypes.c_void_p),
         ("saved_count", ctypes.c_int64),
+        ("grads", ctypes.c_void_p),
+        ("grads_count", ctypes.c_int64),
     ]
 
 
@@ -83,6 +85,8 @@ def lib():
         L.lhaf_gammas.restype = i32
         L.lhaf_saved_count.argtypes = [i32, vp, vp, P(LhOpts)]
         L.lhaf_saved_count.restype = i64
+        L.lhaf_grads_count.argtypes = [i32, vp, vp]
+        L.lhaf_grads_count.restype = i64
         L.lhaf_backward_workspace.argtypes = [i32, vp, vp, i32, P(LhOpts)]
         L.lhaf_backward_workspace.restype = sz
         L.lhaf_backward.argtypes = [i32, vp, i64, i64, vp, i64, vp, vp, vp, vp, vp, vp, i32, vp,
@@ -94,7 +98,7 @@ def lib():
 
 EXPORTED = ["lh_opts_default", "lh_status_string", "lhaf_schedule_count", "lhaf_term_count",
             "lhaf_plan_pairs", "lhaf", "lhaf_repeated", "lhaf_batched_workspace", "lhaf_batched",
-            "lhaf_real", "lhaf_mixed", "lhaf_chain", "lhaf_gammas", "lhaf_saved_count", "lhaf_backward_workspace",
+            "lhaf_real", "lhaf_mixed", "lhaf_chain", "lhaf_gammas", "lhaf_saved_count", "lhaf_grads_count", "lhaf_backward_workspace",
             "lhaf_backward"]
 
 
@@ -104,7 +108,7 @@ def check(status: int) -> None:
 
 
 def make_opts(sum="fds", acc="dd", term_begin=0, term_end=-1, scaled=True, schedule=-1,
-              workspace=None, out_lo=None, saved=None) -> LhOpts:
+              workspace=None, out_lo=None, saved=None, grads=None) -> LhOpts:
     o = LhOpts()
     lib().lh_opts_default(ctypes.byref(o))
     o.sum = _SUMS[sum]
@@ -121,6 +125,9 @@ def make_opts(sum="fds", acc="dd", term_begin=0, term_end=-1, scaled=True, sched
     if saved is not None:
         o.saved = ctypes.c_void_p(saved.data_ptr())
         o.saved_count = saved.numel()
+    if grads is not None:
+        o.grads = ctypes.c_void_p(grads.data_ptr())
+        o.grads_count = grads.numel()
     return o
 
 

@@ -189,11 +189,12 @@ def lhaf_gammas(A, gammas, r=None, *, sum="fds", acc="dd", schedule=-1, return_e
     return (out, err) if return_error else out
 
 
-def lhaf_saved_count(idx_off, r=None, sum="fds") -> int:
-    """Entries of the per-term coefficient store of a batch (complex128)."""
+def lhaf_saved_count(idx_off, r=None, sum="fds", term_begin=0, term_end=-1) -> int:
+    """Entries of the per-term coefficient store of a batch (complex128) over
+    the term range [term_begin, term_end) of every problem."""
     off = np.ascontiguousarray(idx_off, dtype=np.int64)
     rr = None if r is None else np.ascontiguousarray(r, dtype=np.int32)
-    o = Bn.make_opts(sum)
+    o = Bn.make_opts(sum, term_begin=term_begin, term_end=term_end)
     v = int(Bn.lib().lhaf_saved_count(len(off) - 1, Bn.host_ptr(off), Bn.host_ptr(rr),
                                       ctypes.byref(o)))
     if v < 0:
@@ -205,24 +206,39 @@ def _saved_tensor(saved, device):
     if saved is None:
         return None
     if saved.dtype != torch.complex128 or saved.device != device or not saved.is_contiguous():
-        raise ValueError("saved must be a contiguous complex128 tensor on the problems' device")
+        raise ValueError("saved / grads must be a contiguous complex128 tensor on the problems' "
+                         "device")
     return saved
+
+
+def lhaf_grads_count(idx_off, r=None) -> int:
+    """Entries of the per-problem reduced-gradient buffer (complex128) of a
+    batch, for the fused pass (lhaf_batched(..., grads=...))."""
+    off = np.ascontiguousarray(idx_off, dtype=np.int64)
+    rr = None if r is None else np.ascontiguousarray(r, dtype=np.int32)
+    v = int(Bn.lib().lhaf_grads_count(len(off) - 1, Bn.host_ptr(off), Bn.host_ptr(rr)))
+    if v < 0:
+        Bn.check(-v)
+    return v
 
 
 def lhaf_batched(A, gamma, idx=None, idx_off=None, r=None, *, sum="fds", acc="dd",
                  term_begin=0, term_end=-1, scaled=True, schedule=-1, return_error=False,
-                 return_lo=False, workspace=None, saved=None):
+                 return_lo=False, workspace=None, saved=None, grads=None):
     """Many loop hafnians in one persistent launch.  Either a dense stack
     A (B,N,N), gamma (B,N), or a shared base A (M,M), gamma (M) with index
     lists idx[idx_off[b]:idx_off[b+1]] (r: optional multiplicities packed like
     idx).  saved: optional complex128 tensor of lhaf_saved_count(...) entries
-    that receives the per-term coefficients for lhaf_backward."""
+    that receives the per-term coefficients for lhaf_backward.  grads:
+    optional complex128 tensor of lhaf_grads_count(...) entries: the fused
+    pass, which also leaves each problem's gradient there for
+    lhaf_backward(..., grads=...)."""
     A, gamma, Bsz, lda, sA, sg, off, idx_t, rr = _batch_args(A, gamma, idx, idx_off, r)
     out = torch.empty(Bsz, dtype=torch.complex128, device=A.device)
     err = torch.empty(Bsz, dtype=torch.float64, device=A.device)
     lo = torch.zeros(Bsz, dtype=torch.complex128, device=A.device) if return_lo else None
     o = Bn.make_opts(sum, acc, term_begin, term_end, scaled, schedule, None, lo,
-                     _saved_tensor(saved, A.device))
+                     _saved_tensor(saved, A.device), _saved_tensor(grads, A.device))
     need = int(Bn.lib().lhaf_batched_workspace(Bsz, Bn.host_ptr(off), Bn.host_ptr(rr), ctypes.byref(o)))
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
@@ -240,10 +256,14 @@ def lhaf_batched(A, gamma, idx=None, idx_off=None, r=None, *, sum="fds", acc="dd
 
 
 def lhaf_backward(A, gamma, grad_out, idx=None, idx_off=None, r=None, *, sum="fds",
-                  acc="dd", schedule=-1, workspace=None, saved=None):
+                  acc="dd", term_begin=0, term_end=-1, schedule=-1, workspace=None, saved=None,
+                  grads=None):
     """Gradients (dA, dgamma) of the batch in PyTorch's complex convention:
-    grad_out * conj(d lhaf / d input).  saved: the coefficient store written
-    by lhaf_batched on the same batch and sum (skips the Hessenberg phase)."""
+    grad_out * conj(d lhaf / d input).  With a term range, the share of the
+    gradient from those terms of every problem (disjoint ranges add up).
+    saved: the coefficient store written by lhaf_batched on the same batch,
+    sum and term range (skips the Hessenberg phase).  grads: the gradients a
+    fused lhaf_batched(..., grads=...) pass left (skips the term pass)."""
     A, gamma, Bsz, lda, sA, sg, off, idx_t, rr = _batch_args(A, gamma, idx, idx_off, r)
     grad_out = _dev_c128(grad_out, "grad_out").reshape(-1)
     if grad_out.numel() != Bsz:
@@ -251,7 +271,8 @@ def lhaf_backward(A, gamma, grad_out, idx=None, idx_off=None, r=None, *, sum="fd
     base_dim = A.shape[-1]
     dA = torch.empty_like(A)
     dg = torch.empty_like(gamma)
-    o = Bn.make_opts(sum, acc, 0, -1, True, schedule, saved=_saved_tensor(saved, A.device))
+    o = Bn.make_opts(sum, acc, term_begin, term_end, True, schedule,
+                     saved=_saved_tensor(saved, A.device), grads=_saved_tensor(grads, A.device))
     need = int(Bn.lib().lhaf_backward_workspace(Bsz, Bn.host_ptr(off), Bn.host_ptr(rr), base_dim,
                                                 ctypes.byref(o)))
     if workspace is None or workspace.numel() < need:
@@ -272,42 +293,53 @@ def _store_fits(count: int, device, fraction: float) -> bool:
 
 
 class LhafFunction(torch.autograd.Function):
-    """lhaf of a dense batch (A (B,N,N), gamma (B,N)) with the adjoint kernel
-    as backward.  When gradients are needed and the per-term coefficient
-    store fits in `store_fraction` of free device memory, the forward keeps it
-    and the backward skips the Hessenberg phase."""
+    """lhaf of a dense batch (A (B,N,N), gamma (B,N)) with the adjoint kernels
+    as backward.  Modes when gradients are needed:
+      "fused" (default): the forward runs the fused pass -- every term's value
+        and adjoint in one launch -- and keeps only each problem's reduced
+        gradient (LD^2 + 64 complex per problem); the backward maps it to
+        dA, dgamma with grad_out.
+      "recompute": plain forward; the backward repeats every term's spectral
+        work (nothing kept between the passes but A, gamma).
+      "store": the forward keeps every term's series coefficients (16 n bytes
+        per term) when they fit in store_fraction of free device memory, and
+        the backward reads them (else it recomputes)."""
 
     @staticmethod
-    def forward(ctx, A, gamma, sum="fds", acc="dd", r=None, store_fraction=0.5):
-        saved = None
-        if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
-            off = np.arange(A.shape[0] + 1, dtype=np.int64) * A.shape[1]
-            rr = None if r is None else np.asarray(r, dtype=np.int32).reshape(-1)
+    def forward(ctx, A, gamma, sum="fds", acc="dd", r=None, mode="fused", store_fraction=0.5):
+        saved = grads = None
+        need_grad = ctx.needs_input_grad[0] or ctx.needs_input_grad[1]
+        off = np.arange(A.shape[0] + 1, dtype=np.int64) * A.shape[1]
+        rr = None if r is None else np.asarray(r, dtype=np.int32).reshape(-1)
+        if need_grad and mode == "fused":
+            grads = torch.empty(lhaf_grads_count(off, rr), dtype=torch.complex128, device=A.device)
+        elif need_grad and mode == "store":
             count = lhaf_saved_count(off, rr, sum)
             if count > 0 and _store_fits(count, A.device, store_fraction):
                 saved = torch.empty(count, dtype=torch.complex128, device=A.device)
+        elif mode not in ("fused", "recompute", "store"):
+            raise ValueError(f"unknown mode {mode!r}")
         ctx.save_for_backward(A, gamma)
-        ctx.store = saved
+        ctx.store, ctx.grads = saved, grads
         ctx.opts = (sum, acc, r)
-        out = lhaf_batched(A, gamma, r=r, sum=sum, acc=acc, saved=saved)
-        return out
+        return lhaf_batched(A, gamma, r=r, sum=sum, acc=acc, saved=saved, grads=grads)
 
     @staticmethod
     def backward(ctx, grad_out):
         A, gamma = ctx.saved_tensors
         sum, acc, r = ctx.opts
-        # the store stays with the graph (a retained graph's second backward
+        # the buffers stay with the graph (a retained graph's second backward
         # must give the same bits)
         dA, dg = lhaf_backward(A, gamma, grad_out.contiguous(), r=r, sum=sum, acc=acc,
-                               saved=ctx.store)
-        return dA, dg, None, None, None, None
+                               saved=ctx.store, grads=ctx.grads)
+        return dA, dg, None, None, None, None, None
 
 
-def lhaf_autograd(A, gamma, sum="fds", acc="dd", r=None, store_fraction=0.5):
+def lhaf_autograd(A, gamma, sum="fds", acc="dd", r=None, mode="fused", store_fraction=0.5):
     """Differentiable lhaf of one matrix (A (N,N)) or a dense batch (A (B,N,N));
-    store_fraction = 0 always recomputes the per-term coefficients."""
+    mode "fused" (default), "recompute" or "store" (see LhafFunction)."""
     squeeze = A.dim() == 2
     if squeeze:
         A, gamma = A.unsqueeze(0), gamma.unsqueeze(0)
-    out = LhafFunction.apply(A, gamma, sum, acc, r, store_fraction)
+    out = LhafFunction.apply(A, gamma, sum, acc, r, mode, store_fraction)
     return out[0] if squeeze else out

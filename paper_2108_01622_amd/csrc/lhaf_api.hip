@@ -53,16 +53,22 @@ lh_status ensure_device(int& dev) {
   return LH_OK;
 }
 
+// Library-owned workspace of calls without one: reserved once per device at
+// the first such call (256 MiB, or the call's need if larger), so later calls
+// allocate nothing; a call that needs more replaces it by a buffer at least
+// twice as large (waiting for the device first, since queued work may still
+// use the old one).
 lh_status get_scratch(int dev, size_t bytes, void** out) {
   DevState& S = g_dev[dev];
   if (S.scratch_bytes < bytes) {
+    const size_t old = S.scratch_bytes;
     if (S.scratch) {
       (void)hipDeviceSynchronize();
       (void)hipFree(S.scratch);
       S.scratch = nullptr;
       S.scratch_bytes = 0;
     }
-    size_t sz = std::max<size_t>(bytes, 1 << 20);
+    size_t sz = std::max<size_t>(std::max<size_t>(bytes, 2 * old), (size_t)256 << 20);
     if (hipMalloc(&S.scratch, sz) != hipSuccess) return LH_ENOMEM;
     S.scratch_bytes = sz;
   }
@@ -156,6 +162,7 @@ struct Plan {
   int bmax = 1, nmax = 0;
   int grid = 1;
   int64_t saved_need = 0;  // entries of the per-term coefficient store
+  int64_t grads_need = 0;  // entries of the per-problem reduced gradients
   Layout lay;
 };
 
@@ -192,17 +199,15 @@ lh_status build_plan(std::vector<ProblemIn>& pin, const lh_opts& o, int dev, Pla
     Prob& P = pl.probs[b];
     if (!fill_prob(pin[b].plan, o.sum, o.term_begin, o.term_end, o.scaled != 0 || for_backward, &P))
       return LH_ESIZE;
-    if (for_backward) {
-      P.t0 = 0;
-      P.t1 = P.T;
-    }
     P.c_off = (int64_t)pl.c_elems;
     pl.c_elems += (size_t)(8 * P.B) * (8 * P.B) + 64;
     P.s_off = -1;
     if (P.n > 0) {
       P.s_off = pl.saved_need;
-      pl.saved_need += P.T * P.n;
+      pl.saved_need += (P.t1 - P.t0) * P.n;
     }
+    P.r_off = pl.grads_need;
+    pl.grads_need += (int64_t)bwd_item_elems(P.B);
     pl.aoff[b] = pin[b].a_off;
     pl.goff[b] = pin[b].g_off;
     pl.ioff[b] = pin[b].i_off;
@@ -284,25 +289,79 @@ lh_status build_plan(std::vector<ProblemIn>& pin, const lh_opts& o, int dev, Pla
 // launch a planned forward evaluation
 lh_status run_forward(Plan& pl, const lh_c128* A, int64_t lda, const lh_c128* g,
                       const int32_t* idx, lh_c128* out, double* err, const lh_opts& o,
-                      void* ws, hipStream_t st, int dev);
+                      void* ws, hipStream_t st, int dev, bool pageable = false);
 
+// Plan tables reach the device through a small ring of pinned staging
+// buffers per device.  Each buffer's copy is followed by an event; a buffer is
+// reused only after its previous copy has completed, so a call never waits
+// for earlier kernels on the stream (only, with more than kStageRing uploads
+// in flight, for the oldest upload's copy).
+constexpr int kStageRing = 8;
+struct StageBuf {
+  void* host = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+// Calls that must not allocate device or pinned memory stage
+// through a separate ring of pageable host buffers (std::vector, no pinned
+// or device allocation); the runtime copies those through its own staging.
+struct PageBuf {
+  std::vector<char> host;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
 std::mutex g_stage_mu;
-void* g_stage[64] = {nullptr};
-size_t g_stage_bytes[64] = {0};
+StageBuf g_stage[64][kStageRing];
+int g_stage_next[64] = {0};
+PageBuf g_pstage[64][kStageRing];
+int g_pstage_next[64] = {0};
 
-lh_status upload_plan(const Plan& pl, char* base, hipStream_t st, int dev) {
+lh_status upload_plan(const Plan& pl, char* base, hipStream_t st, int dev, bool pageable) {
   const size_t nprob = pl.probs.size(), nit = pl.items.size();
   const size_t span = pl.lay.cdata;  // tables occupy [probs, cdata)
   std::lock_guard<std::mutex> lk(g_stage_mu);
-  if (g_stage_bytes[dev] < span) {
-    if (g_stage[dev]) (void)hipHostFree(g_stage[dev]);
-    g_stage[dev] = nullptr;
-    g_stage_bytes[dev] = 0;
-    size_t sz = std::max<size_t>(span, 1 << 16);
-    if (hipHostMalloc(&g_stage[dev], sz, hipHostMallocDefault) != hipSuccess) return LH_ENOMEM;
-    g_stage_bytes[dev] = sz;
+  hipEvent_t* done;
+  bool* pending;
+  char* h;
+  if (pageable) {
+    PageBuf& S = g_pstage[dev][g_pstage_next[dev]];
+    g_pstage_next[dev] = (g_pstage_next[dev] + 1) % kStageRing;
+    if (!S.done && hipEventCreateWithFlags(&S.done, hipEventDisableTiming) != hipSuccess) {
+      S.done = nullptr;
+      return LH_EHIP;
+    }
+    if (S.pending) {
+      if (hipEventSynchronize(S.done) != hipSuccess) return LH_EHIP;
+      S.pending = false;
+    }
+    if (S.host.size() < span) S.host.resize(span);
+    done = &S.done;
+    pending = &S.pending;
+    h = S.host.data();
+  } else {
+    StageBuf& S = g_stage[dev][g_stage_next[dev]];
+    g_stage_next[dev] = (g_stage_next[dev] + 1) % kStageRing;
+    if (!S.done && hipEventCreateWithFlags(&S.done, hipEventDisableTiming) != hipSuccess) {
+      S.done = nullptr;
+      return LH_EHIP;
+    }
+    if (S.pending) {
+      if (hipEventSynchronize(S.done) != hipSuccess) return LH_EHIP;
+      S.pending = false;
+    }
+    if (S.bytes < span) {
+      if (S.host) (void)hipHostFree(S.host);
+      S.host = nullptr;
+      S.bytes = 0;
+      size_t sz = std::max<size_t>(span, 1 << 16);
+      if (hipHostMalloc(&S.host, sz, hipHostMallocDefault) != hipSuccess) return LH_ENOMEM;
+      S.bytes = sz;
+    }
+    done = &S.done;
+    pending = &S.pending;
+    h = static_cast<char*>(S.host);
   }
-  char* h = static_cast<char*>(g_stage[dev]);
   std::memset(h, 0, span);
   std::memcpy(h + pl.lay.probs, pl.probs.data(), sizeof(Prob) * nprob);
   if (nit) std::memcpy(h + pl.lay.items, pl.items.data(), sizeof(Item) * nit);
@@ -312,7 +371,8 @@ lh_status upload_plan(const Plan& pl, char* base, hipStream_t st, int dev) {
   const size_t off = pl.lay.probs;
   if (hipMemcpyAsync(base + off, h + off, span - off, hipMemcpyHostToDevice, st) != hipSuccess)
     return LH_EHIP;
-  if (hipStreamSynchronize(st) != hipSuccess) return LH_EHIP;
+  if (hipEventRecord(*done, st) != hipSuccess) return LH_EHIP;
+  *pending = true;
   return LH_OK;
 }
 
@@ -336,18 +396,16 @@ static PersistArgs persist_args(const Plan& pl, char* base, size_t lds, hipStrea
   return a;
 }
 
-// Copy the host plan (problem table, item list, offsets) into the workspace.
-// The tables go through one pinned staging buffer per device; the copy is
-// waited for before returning, so the staging buffer and the plan can be
-// reused by the next call.
-lh_status upload_plan(const Plan& pl, char* base, hipStream_t st, int dev);
+// Copy the host plan (problem table, item list, offsets) into the workspace,
+// stream-ordered (the host does not wait for the stream).
+lh_status upload_plan(const Plan& pl, char* base, hipStream_t st, int dev, bool pageable = false);
 
 lh_status run_forward(Plan& pl, const lh_c128* A, int64_t lda, const lh_c128* g,
                       const int32_t* idx, lh_c128* out, double* err, const lh_opts& o, void* ws,
-                      hipStream_t st, int dev) {
+                      hipStream_t st, int dev, bool pageable) {
   char* base = static_cast<char*>(ws);
   const int nprob = (int)pl.probs.size();
-  lh_status us = upload_plan(pl, base, st, dev);
+  lh_status us = upload_plan(pl, base, st, dev, pageable);
   if (us != LH_OK) return us;
   hipLaunchKernelGGL(pack_kernel, dim3(nprob), dim3(256), 0, st,
                      reinterpret_cast<const Prob*>(base + pl.lay.probs),
@@ -376,7 +434,7 @@ lh_status run_forward(Plan& pl, const lh_c128* A, int64_t lda, const lh_c128* g,
   hipLaunchKernelGGL(finalize_kernel, dim3((nprob + 127) / 128), dim3(128), 0, st,
                      reinterpret_cast<const Prob*>(base + pl.lay.probs), nprob,
                      reinterpret_cast<const Partial*>(base + pl.lay.parts), out, o.out_lo, err,
-                     acc_dd);
+                     acc_dd, 0);
   if (hipGetLastError() != hipSuccess) return LH_EHIP;
   return LH_OK;
 }
@@ -483,8 +541,17 @@ static lh_status validate_opts(const lh_opts* opts, lh_opts& o) {
   if (o.sum != LH_SUM_ET && o.sum != LH_SUM_FDS) return LH_EINVAL;
   if (o.acc != LH_ACC_FP64 && o.acc != LH_ACC_DD) return LH_EINVAL;
   if (o.saved && o.saved_count < 0) return LH_EINVAL;
+  if (o.grads && o.grads_count < 0) return LH_EINVAL;
   return LH_OK;
 }
+
+static lh_status backward_impl(int32_t B, const lh_c128* A_base, int64_t lda, int64_t stride_A,
+                               const lh_c128* gamma_base, int64_t stride_g, const int32_t* idx,
+                               const int64_t* idx_off, const int32_t* r, const lh_c128* grad_out,
+                               lh_c128* dA, lh_c128* dgamma, int32_t base_dim, bool fused,
+                               lh_c128* out, double* err_est, void* workspace, size_t ws_bytes,
+                               const lh_opts& o, hipStream_t st, bool query_only,
+                               size_t* need_bytes);
 
 static lh_status batched_impl(int32_t B, const lh_c128* A_base, int64_t lda, int64_t stride_A,
                               const lh_c128* gamma_base, int64_t stride_g, const int32_t* idx,
@@ -492,6 +559,29 @@ static lh_status batched_impl(int32_t B, const lh_c128* A_base, int64_t lda, int
                               double* err_est, void* workspace, size_t ws_bytes,
                               const lh_opts& o, hipStream_t st, bool query_only,
                               size_t* need_bytes) {
+  if (o.grads) {  // fused value + gradient pass
+    if (!query_only && !out) return LH_EINVAL;
+    void* ws = workspace;
+    if (!ws && !query_only) {
+      size_t need = 0;
+      lh_status qs = backward_impl(B, nullptr, 1, 0, nullptr, 0, nullptr, idx_off, r, nullptr,
+                                   nullptr, nullptr, 1, true, nullptr, nullptr, nullptr, 0, o, st,
+                                   true, &need);
+      if (qs != LH_OK) return qs;
+      int dev = 0;
+      qs = ensure_device(dev);
+      if (qs != LH_OK) return qs;
+      std::lock_guard<std::mutex> lk(g_mu);
+      qs = get_scratch(dev, need, &ws);
+      if (qs != LH_OK) return qs;
+      return backward_impl(B, A_base, lda, stride_A, gamma_base, stride_g, idx, idx_off, r,
+                           nullptr, nullptr, nullptr, 1, true, out, err_est, ws, need, o, st,
+                           false, nullptr);
+    }
+    return backward_impl(B, A_base, lda, stride_A, gamma_base, stride_g, idx, idx_off, r, nullptr,
+                         nullptr, nullptr, 1, true, out, err_est, ws, ws_bytes, o, st, query_only,
+                         need_bytes);
+  }
   std::vector<ProblemIn> pin;
   lh_status ps = parse_problems(B, idx_off, r, stride_A, stride_g, pin);
   if (ps != LH_OK) return ps;
@@ -507,10 +597,7 @@ static lh_status batched_impl(int32_t B, const lh_c128* A_base, int64_t lda, int
     *need_bytes = pl.lay.total;
     return LH_OK;
   }
-  if (o.saved) {
-    if (o.term_begin != 0 || o.term_end != -1) return LH_EUNSUPPORTED;
-    if (o.saved_count < pl.saved_need) return LH_ENOMEM;
-  }
+  if (o.saved && o.saved_count < pl.saved_need) return LH_ENOMEM;
   if (B == 0) return LH_OK;
   if (!A_base || !gamma_base || !out || lda < 1) return LH_EINVAL;
   void* ws = workspace;
@@ -676,11 +763,20 @@ static lh_status multi_impl(const PairPlan& plan, const lh_c128* A, int64_t lda,
   return LH_OK;
 }
 
+// Gradient pass over a batch.  Three uses:
+//   lhaf_backward                : term pass -> per-problem gradients in the
+//                                  workspace -> scatter with grad_out
+//   lhaf_backward + opts->grads  : scatter from the gradients a fused pass
+//                                  left in opts->grads (no term pass)
+//   lhaf_batched + opts->grads   : fused pass: term pass that also sums the
+//                                  values (out, err_est), gradients into
+//                                  opts->grads (no scatter)
 static lh_status backward_impl(int32_t B, const lh_c128* A_base, int64_t lda, int64_t stride_A,
                                const lh_c128* gamma_base, int64_t stride_g, const int32_t* idx,
                                const int64_t* idx_off, const int32_t* r, const lh_c128* grad_out,
-                               lh_c128* dA, lh_c128* dgamma, int32_t base_dim, void* workspace,
-                               size_t ws_bytes, const lh_opts& o, hipStream_t st, bool query_only,
+                               lh_c128* dA, lh_c128* dgamma, int32_t base_dim, bool fused,
+                               lh_c128* out, double* err_est, void* workspace, size_t ws_bytes,
+                               const lh_opts& o, hipStream_t st, bool query_only,
                                size_t* need_bytes) {
   std::vector<ProblemIn> pin;
   lh_status ps = parse_problems(B, idx_off, r, stride_A, stride_g, pin);
@@ -688,9 +784,10 @@ static lh_status backward_impl(int32_t B, const lh_c128* A_base, int64_t lda, in
   int dev = 0;
   lh_status s = ensure_device(dev);
   if (s != LH_OK) return s;
+  const bool from_grads = !fused && o.grads != nullptr;
+  // the gradient of a term range is that range's share of the full gradient
+  // (FDS prefactor included), so slices add up
   lh_opts ob = o;
-  ob.term_begin = 0;
-  ob.term_end = -1;
   ob.scaled = 1;
   Plan pl;
   s = build_plan(pin, ob, dev, pl, true);
@@ -702,16 +799,29 @@ static lh_status backward_impl(int32_t B, const lh_c128* A_base, int64_t lda, in
   }
   gtot = std::max<size_t>(gtot, 64);
   const size_t scr = (size_t)pl.grid * bwd_wave_scratch_elems(pl.bmax);
-  const size_t off_g = pl.lay.total;
-  const size_t off_s = align_up(off_g + gtot * sizeof(cd));
-  const size_t total = align_up(off_s + scr * sizeof(cd));
+  size_t off_g = 0, off_r = 0, off_s = 0, total = pl.lay.total;
+  if (!from_grads) {
+    off_g = pl.lay.total;
+    off_r = align_up(off_g + gtot * sizeof(cd));
+    off_s = align_up(off_r + (fused ? 0 : (size_t)pl.grads_need * sizeof(cd)));
+    total = align_up(off_s + scr * sizeof(cd));
+  }
   if (query_only) {
     *need_bytes = total;
     return LH_OK;
   }
+  if (o.grads && o.grads_count < pl.grads_need) return LH_ENOMEM;
+  if (fused && o.saved) return LH_EUNSUPPORTED;
   if (B == 0) return LH_OK;
-  if (!A_base || !gamma_base || !grad_out || !dA || !dgamma || lda < 1) return LH_EINVAL;
-  if (stride_A == 0 && base_dim < 1) return LH_EINVAL;
+  if (!A_base || !gamma_base || lda < 1 || (fused && !out)) return LH_EINVAL;
+  if (!fused) {
+    if (!grad_out || !dA || !dgamma) return LH_EINVAL;
+    if (base_dim < 1 || base_dim > kMaxRows || lda < base_dim) return LH_EINVAL;
+    if (!idx) {  // without index lists, problem b's vertices are rows 0..N_b-1
+      for (int b = 0; b < B; ++b)
+        if (idx_off[b + 1] - idx_off[b] > base_dim) return LH_EINVAL;
+    }
+  }
   if (!workspace) return LH_EINVAL;
   if (ws_bytes < total) return LH_ENOMEM;
   if (o.saved && o.saved_count < pl.saved_need) return LH_ENOMEM;
@@ -719,45 +829,54 @@ static lh_status backward_impl(int32_t B, const lh_c128* A_base, int64_t lda, in
   s = upload_plan(pl, base, st, dev);
   if (s != LH_OK) return s;
   const int nprob = (int)pl.probs.size();
-  hipLaunchKernelGGL(pack_kernel, dim3(nprob), dim3(256), 0, st,
-                     reinterpret_cast<const Prob*>(base + pl.lay.probs),
-                     reinterpret_cast<const int64_t*>(base + pl.lay.aoff),
-                     reinterpret_cast<const int64_t*>(base + pl.lay.goff),
-                     reinterpret_cast<const int64_t*>(base + pl.lay.ioff), A_base, lda, gamma_base,
-                     idx, reinterpret_cast<cd*>(base + pl.lay.cdata),
-                     reinterpret_cast<int*>(base + pl.lay.counter));
-  if (hipGetLastError() != hipSuccess) return LH_EHIP;
-  cd* gsl = reinterpret_cast<cd*>(base + off_g);
-  cd* scratch = reinterpret_cast<cd*>(base + off_s);
-  if (!pl.items.empty()) {
-    const size_t lds = bwd_lds_bytes(pl.bmax, std::max(pl.nmax, 1));
-    const PersistArgs pa = persist_args(pl, base, lds, st);
-    const cd* wsc = reinterpret_cast<const cd*>(base + pl.lay.cdata);
-    const cd* sv = reinterpret_cast<const cd*>(o.saved);
-    hipError_t e;
-    switch (pl.bmax) {
-#define LH_BCASE(BB) \
-  case BB: e = launch_backward<BB>(pa, wsc, gsl, scratch, sv); break;
-      LH_BCASE(1) LH_BCASE(2) LH_BCASE(3) LH_BCASE(4) LH_BCASE(5) LH_BCASE(6) LH_BCASE(7)
-      default: LH_BCASE(8)
-#undef LH_BCASE
-    }
-    if (e != hipSuccess) return LH_EHIP;
+  const Prob* probs = reinterpret_cast<const Prob*>(base + pl.lay.probs);
+  const int acc_dd = o.acc == LH_ACC_DD ? 1 : 0;
+  cd* grads = from_grads || fused ? reinterpret_cast<cd*>(o.grads)
+                                  : reinterpret_cast<cd*>(base + off_r);
+  if (!from_grads) {
+    hipLaunchKernelGGL(pack_kernel, dim3(nprob), dim3(256), 0, st, probs,
+                       reinterpret_cast<const int64_t*>(base + pl.lay.aoff),
+                       reinterpret_cast<const int64_t*>(base + pl.lay.goff),
+                       reinterpret_cast<const int64_t*>(base + pl.lay.ioff), A_base, lda,
+                       gamma_base, idx, reinterpret_cast<cd*>(base + pl.lay.cdata),
+                       reinterpret_cast<int*>(base + pl.lay.counter));
     if (hipGetLastError() != hipSuccess) return LH_EHIP;
+    cd* gsl = reinterpret_cast<cd*>(base + off_g);
+    cd* scratch = reinterpret_cast<cd*>(base + off_s);
+    Partial* parts = fused ? reinterpret_cast<Partial*>(base + pl.lay.parts) : nullptr;
+    if (!pl.items.empty()) {
+      const size_t lds = bwd_lds_bytes(pl.bmax, std::max(pl.nmax, 1));
+      const PersistArgs pa = persist_args(pl, base, lds, st);
+      const cd* wsc = reinterpret_cast<const cd*>(base + pl.lay.cdata);
+      const cd* sv = reinterpret_cast<const cd*>(o.saved);
+      hipError_t e;
+      switch (pl.bmax) {
+#define LH_BCASE(BB) \
+  case BB: e = launch_backward<BB>(pa, wsc, gsl, scratch, sv, parts, acc_dd); break;
+        LH_BCASE(1) LH_BCASE(2) LH_BCASE(3) LH_BCASE(4) LH_BCASE(5) LH_BCASE(6) LH_BCASE(7)
+        default: LH_BCASE(8)
+#undef LH_BCASE
+      }
+      if (e != hipSuccess) return LH_EHIP;
+    }
+    hipLaunchKernelGGL(greduce_kernel, dim3(nprob), dim3(256), 0, st, probs, gsl, grads);
+    if (hipGetLastError() != hipSuccess) return LH_EHIP;
+    if (fused) {
+      hipLaunchKernelGGL(finalize_kernel, dim3((nprob + 127) / 128), dim3(128), 0, st, probs,
+                         nprob, reinterpret_cast<const Partial*>(base + pl.lay.parts), out,
+                         o.out_lo, err_est, acc_dd, o.scaled ? 0 : 1);
+      return hipGetLastError() == hipSuccess ? LH_OK : LH_EHIP;
+    }
   }
-  hipLaunchKernelGGL(greduce_kernel, dim3(nprob), dim3(256), 0, st,
-                     reinterpret_cast<const Prob*>(base + pl.lay.probs), gsl);
-  if (hipGetLastError() != hipSuccess) return LH_EHIP;
   if (stride_A != 0) {
-    hipLaunchKernelGGL(scatter_dense_kernel, dim3(nprob), dim3(256), 0, st,
-                       reinterpret_cast<const Prob*>(base + pl.lay.probs), gsl, grad_out, dA, lda,
-                       stride_A, dgamma, stride_g);
+    hipLaunchKernelGGL(scatter_dense_kernel, dim3(nprob), dim3(256), 0, st, probs, grads,
+                       reinterpret_cast<const int64_t*>(base + pl.lay.ioff), idx, grad_out, dA,
+                       lda, stride_A, dgamma, stride_g, base_dim);
   } else {
     const int64_t E = (int64_t)base_dim * base_dim + base_dim;
     hipLaunchKernelGGL(scatter_shared_kernel, dim3((unsigned)((E + 127) / 128)), dim3(128), 0, st,
-                       reinterpret_cast<const Prob*>(base + pl.lay.probs), nprob,
-                       reinterpret_cast<const int64_t*>(base + pl.lay.ioff), idx, gsl, grad_out,
-                       dA, lda, dgamma, base_dim);
+                       probs, nprob, reinterpret_cast<const int64_t*>(base + pl.lay.ioff), idx,
+                       grads, grad_out, dA, lda, dgamma, base_dim);
   }
   if (hipGetLastError() != hipSuccess) return LH_EHIP;
   return LH_OK;
@@ -775,6 +894,7 @@ lh_status lhaf_mixed(const lh_c128* A, int64_t lda, const lh_c128* gamma, const 
     tot += n[i];
   }
   if (2 * tot > kMaxN || 2 * (int64_t)M > kMaxRows) return LH_ESIZE;
+  if (o.grads) return LH_EUNSUPPORTED;
   if (M > 0 && (!A || !gamma || lda < 2 * (int64_t)M)) return LH_EINVAL;
   int dev = 0;
   s = ensure_device(dev);
@@ -790,10 +910,7 @@ lh_status lhaf_mixed(const lh_c128* A, int64_t lda, const lh_c128* gamma, const 
   Plan pl;
   s = build_plan(pin, o, dev, pl, false);
   if (s != LH_OK) return s;
-  if (o.saved) {
-    if (o.term_begin != 0 || o.term_end != -1) return LH_EUNSUPPORTED;
-    if (o.saved_count < pl.saved_need) return LH_ENOMEM;
-  }
+  if (o.saved && o.saved_count < pl.saved_need) return LH_ENOMEM;
   void* ws = o.workspace;
   std::unique_lock<std::mutex> lk(g_mu, std::defer_lock);
   if (!ws) {
@@ -811,7 +928,7 @@ lh_status lhaf_real(const double* A, int64_t lda, const double* gamma, const int
   lh_opts o;
   lh_status s = validate_opts(opts, o);
   if (s != LH_OK) return s;
-  if (o.saved || o.out_lo) return LH_EUNSUPPORTED;
+  if (o.saved || o.out_lo || o.grads) return LH_EUNSUPPORTED;
   if (M < 0 || !out) return LH_EINVAL;
   PairPlan pp;
   if (r) {
@@ -885,7 +1002,7 @@ lh_status lhaf_chain(const lh_c128* A, int64_t lda, const lh_c128* gamma, const 
   lh_status s = validate_opts(opts, o);
   if (s != LH_OK) return s;
   if (o.sum != LH_SUM_ET) return LH_EUNSUPPORTED;
-  if (o.saved) return LH_EUNSUPPORTED;
+  if (o.saved || o.grads) return LH_EUNSUPPORTED;
   if (M < 1 || !r || !out || !A || !gamma || lda < M || mode_b < 0 || mode_b >= M || n_cut < 0)
     return LH_EINVAL;
   if (M > kMaxRows) return LH_ESIZE;
@@ -944,7 +1061,7 @@ lh_status lhaf_gammas(const lh_c128* A, int64_t lda, const lh_c128* gammas, int6
   lh_opts o;
   lh_status s = validate_opts(opts, o);
   if (s != LH_OK) return s;
-  if (o.saved) return LH_EUNSUPPORTED;
+  if (o.saved || o.grads) return LH_EUNSUPPORTED;
   if (M < 0 || G < 1 || !out || (M > 0 && (!A || !gammas || lda < M || ldg < M))) return LH_EINVAL;
   if (G > 64) return LH_ESIZE;
   PairPlan pp;
@@ -984,7 +1101,22 @@ int64_t lhaf_saved_count(int32_t B, const int64_t* idx_off, const int32_t* r, co
   if (s != LH_OK) return -s;
   int64_t tot = 0;
   for (auto& pi : pin) {
-    if (pi.plan.n > 0) tot += term_count(pi.plan, o.sum == LH_SUM_FDS ? 1 : 0, nullptr) * pi.plan.n;
+    Prob P;
+    if (!fill_prob(pi.plan, o.sum, o.term_begin, o.term_end, true, &P)) return -LH_ESIZE;
+    if (P.n > 0) tot += (P.t1 - P.t0) * P.n;
+  }
+  return tot;
+}
+
+int64_t lhaf_grads_count(int32_t B, const int64_t* idx_off, const int32_t* r) {
+  std::vector<ProblemIn> pin;
+  lh_status s = parse_problems(B, idx_off, r, 0, 0, pin);
+  if (s != LH_OK) return -s;
+  int64_t tot = 0;
+  for (auto& pi : pin) {
+    Prob P;
+    if (!fill_prob(pi.plan, LH_SUM_FDS, 0, -1, true, &P)) return -LH_ESIZE;
+    tot += (int64_t)bwd_item_elems(P.B);
   }
   return tot;
 }
@@ -995,7 +1127,7 @@ size_t lhaf_backward_workspace(int32_t B, const int64_t* idx_off, const int32_t*
   if (validate_opts(opts, o) != LH_OK) return 0;
   size_t need = 0;
   if (backward_impl(B, nullptr, 1, 0, nullptr, 0, nullptr, idx_off, r, nullptr, nullptr, nullptr,
-                    base_dim, nullptr, 0, o, nullptr, true, &need) != LH_OK)
+                    base_dim, false, nullptr, nullptr, nullptr, 0, o, nullptr, true, &need) != LH_OK)
     return 0;
   return need;
 }
@@ -1009,8 +1141,8 @@ lh_status lhaf_backward(int32_t B, const lh_c128* A_base, int64_t lda, int64_t s
   lh_status s = validate_opts(opts, o);
   if (s != LH_OK) return s;
   return backward_impl(B, A_base, lda, stride_A, gamma_base, stride_g, idx, idx_off, r, grad_out,
-                       dA, dgamma, base_dim, workspace, ws_bytes, o, (hipStream_t)stream, false,
-                       nullptr);
+                       dA, dgamma, base_dim, false, nullptr, nullptr, workspace, ws_bytes, o,
+                       (hipStream_t)stream, false, nullptr);
 }
 
 }  // extern "C"

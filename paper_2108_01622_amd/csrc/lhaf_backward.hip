@@ -338,12 +338,18 @@ __device__ __forceinline__ void combine_powers(double (&Rr)[B][B], double (&Ri)[
 // G[LD*LD] (accumulated as sum_t c_t d_{pair(j)} M_t[j][c], M = (d f/d W)^T)
 // and G[LD*LD + l] (d f / d v_l).  With a coefficient store written by the
 // forward pass, the a_k are read instead of recomputed.
+//
+// With `part` (fused pass, no store), the item also accumulates its share of
+// the value: the recomputed series give f = sum_k q_k L_{n-k} of every term,
+// added as c_t f_t into a double-double (acc_dd) or plain partial, exactly as
+// the forward kernel does.
 template <int B, bool kStage>
 __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, const int64_t t1,
                                              const cd* __restrict__ Cp,
                                              const cd* __restrict__ vp, cd* __restrict__ G,
                                              cd* __restrict__ scr, LdsView& L,
-                                             const cd* __restrict__ saved) {
+                                             const cd* __restrict__ saved,
+                                             Partial* __restrict__ part, const int acc_dd) {
   constexpr int LD = 8 * B;
   constexpr int S = kStage ? LD : 64;    // stride of the Krylov vectors
   const int lane = threadIdx.x & 63;
@@ -364,6 +370,8 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
   int s = 1;
   while (s * s < n) ++s;
   const int Q = (n + s - 1) / s - 1;
+  dd accr = {0.0, 0.0}, acci = {0.0, 0.0};
+  double sabs = 0.0;
 
   TermIter it = term_begin(P, t0, lane);
   for (int64_t t = t0; t < t1; ++t) {
@@ -389,7 +397,7 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
     const double dlane = lane < m ? dsh : 0.0;
 
     cd asaved = czero();
-    if (saved && lane >= 1 && lane <= n) asaved = saved[P.s_off + t * n + (lane - 1)];
+    if (saved && lane >= 1 && lane <= n) asaved = saved[P.s_off + (t - P.t0) * n + (lane - 1)];
     double Wr[B][B], Wi[B][B];
     load_w<B>(Cp, dcol, p, q, Wr, Wi);
     krylov_b<B, S, kStage>(Wr, Wi, dlane, vp, m, H, n, p, q, lane, bv, L, saved == nullptr);
@@ -398,6 +406,19 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
     } else {
       spectral_series<B>(Wr, Wi, m, n, p, q, lane, L);
       if (lane >= 1 && lane <= n) acoef[lane] = series_coef(L, n, lane);
+      if (part) {
+        cd f = czero();
+        if (lane <= n) f = cmul(L.ser[lane], L.ser[33 + n - lane]);
+        f = mk(sum_col8(sum_row8(f.r)), sum_col8(sum_row8(f.i)));
+        if (acc_dd) {
+          dd_add_prod(accr, coef, f.r);
+          dd_add_prod(acci, coef, f.i);
+        } else {
+          accr.hi = fma(coef, f.r, accr.hi);
+          acci.hi = fma(coef, f.i, acci.hi);
+        }
+        sabs = fma(fabs(coef), sqrt(cabs2(f)), sabs);
+      }
     }
     lane_sync<kStage>();
 
@@ -459,6 +480,16 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
     accumulate_g<B>(G, coef, drow, Rr, Ri, p, q);
     lane_sync<kStage>();
   }
+  if (part && lane == 0) {
+    Partial pr;
+    pr.hr = accr.hi;
+    pr.hi = acci.hi;
+    pr.lr = accr.lo;
+    pr.li = acci.lo;
+    pr.abs_sum = sabs;
+    pr.pad0 = pr.pad1 = pr.pad2 = 0.0;
+    *part = pr;
+  }
 }
 
 template <int BMAX>
@@ -475,7 +506,8 @@ __global__ LH_BWD_ATTR void backward_kernel(const Prob* __restrict__ probs,
                                                       int* counter, const cd* __restrict__ ws,
                                                       cd* __restrict__ gslots,
                                                       cd* __restrict__ scratch, int nmax,
-                                                      const cd* __restrict__ saved) {
+                                                      const cd* __restrict__ saved,
+                                                      Partial* __restrict__ parts, int acc_dd) {
   extern __shared__ __align__(16) char lds_raw[];
   LdsView L = carve(lds_raw, nmax);
   const int lane = threadIdx.x & 63;
@@ -492,7 +524,9 @@ __global__ LH_BWD_ATTR void backward_kernel(const Prob* __restrict__ probs,
     switch (P.B) {
 #define LH_BCASE(BB)                                                                   \
   case BB:                                                                             \
-    if (BB <= BMAX) run_item_bwd<(BB <= BMAX ? BB : 1), (BMAX <= kStageMaxB)>(P, I.t0, I.t1, Cp, vp, G, scr, L, saved); \
+    if (BB <= BMAX)                                                                    \
+      run_item_bwd<(BB <= BMAX ? BB : 1), (BMAX <= kStageMaxB)>(                         \
+          P, I.t0, I.t1, Cp, vp, G, scr, L, saved, parts ? parts + I.pad : nullptr, acc_dd); \
     break;
       LH_BCASE(1)
       LH_BCASE(2)
@@ -510,17 +544,19 @@ __global__ LH_BWD_ATTR void backward_kernel(const Prob* __restrict__ probs,
 }
 
 #ifdef LH_COMMON_KERNELS
-// Sum the item gradients of each problem (in item order) into its first slot.
-__global__ void greduce_kernel(const Prob* __restrict__ probs, cd* __restrict__ gslots) {
+// Sum the item gradients of each problem (in item order) into the problem's
+// reduced gradient at dst + r_off (0 when no item of the problem ran).
+__global__ void greduce_kernel(const Prob* __restrict__ probs, const cd* __restrict__ gslots,
+                               cd* __restrict__ dst) {
   const Prob& P = probs[blockIdx.x];
-  if (P.n_items <= 1) return;
   const int LD = 8 * P.B;
   const int E = LD * LD + 64;
-  cd* base = gslots + P.g_off;
+  const cd* base = gslots + P.g_off;
+  cd* out = dst + P.r_off;
   for (int e = threadIdx.x; e < E; e += blockDim.x) {
-    cd acc = base[e];
-    for (int k = 1; k < P.n_items; ++k) acc = cadd(acc, base[(int64_t)k * E + e]);
-    base[e] = acc;
+    cd acc = czero();
+    for (int k = 0; k < P.n_items; ++k) acc = cadd(acc, base[(int64_t)k * E + e]);
+    out[e] = acc;
   }
 }
 
@@ -531,31 +567,39 @@ __device__ __forceinline__ cd grad_c(const Prob& P, const cd* __restrict__ G, in
   return cscale(P.scale, G[pi * LD + c]);
 }
 
-// Dense batch: problem b owns dA_b (N x N, lda) and dgamma_b; one block per
-// problem gathers every entry from the positions of its two vertices.
-__global__ void scatter_dense_kernel(const Prob* __restrict__ probs, const cd* __restrict__ gslots,
+// Dense batch: problem b owns dA_b (base_dim x base_dim, lda) and dgamma_b
+// (base_dim); one block per problem writes every entry of both from the
+// problem's reduced gradient (grads + r_off).  Entry
+// (x, y) gathers the reduced-gradient entries of the vertices whose index
+// list entry maps to matrix rows x and y (idx, or the identity without one);
+// rows that no vertex maps to get 0.
+__global__ void scatter_dense_kernel(const Prob* __restrict__ probs, const cd* __restrict__ grads,
+                                     const int64_t* __restrict__ ioff,
+                                     const int32_t* __restrict__ idx,
                                      const lh_c128* __restrict__ grad_out, lh_c128* dA, int64_t lda,
-                                     int64_t strideA, lh_c128* dg, int64_t strideG) {
+                                     int64_t strideA, lh_c128* dg, int64_t strideG, int base_dim) {
   __shared__ short first[kMaxRows];
   __shared__ short nxt[64];
   const int b = blockIdx.x;
   const Prob& P = probs[b];
-  const int N = P.Nvert;
+  const int N = base_dim;
+  const int32_t* ib = idx ? idx + ioff[b] : nullptr;
   for (int x = threadIdx.x; x < N; x += blockDim.x) first[x] = -1;
   if (threadIdx.x < 64) nxt[threadIdx.x] = -1;
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int c = P.m - 1; c >= 0; --c) {
       const int x = P.pos[c];
-      if (x >= 0) {
-        nxt[c] = first[x];
-        first[x] = c;
+      const int row = x < 0 ? -1 : (ib ? ib[x] : x);
+      if (row >= 0 && row < N) {
+        nxt[c] = first[row];
+        first[row] = c;
       }
     }
   }
   __syncthreads();
   const int LD = 8 * P.B;
-  const cd* G = gslots + P.g_off;
+  const cd* G = grads + P.r_off;
   const lh_c128 go = grad_out[b];
   const cd gout = mk(go.re, go.im);
   lh_c128* dAb = dA + (int64_t)b * strideA;
@@ -564,15 +608,16 @@ __global__ void scatter_dense_kernel(const Prob* __restrict__ probs, const cd* _
     cd val = czero();
     if (e < N * N) {
       const int x = e / N, y = e % N;
-      for (int c = first[x]; c >= 0; c = nxt[c])
-        for (int i = first[y]; i >= 0; i = nxt[i]) {
-          if (c != i) {
-            val = cadd(val, cscale(0.5, cadd(grad_c(P, G, LD, c, i), grad_c(P, G, LD, i, c))));
-          } else {
-            const int pr = c < P.H ? c : c - P.H;
-            if ((P.diag_keep_mask >> pr) & 1) val = cadd(val, grad_c(P, G, LD, c, c));
+      if (P.n > 0)
+        for (int c = first[x]; c >= 0; c = nxt[c])
+          for (int i = first[y]; i >= 0; i = nxt[i]) {
+            if (c != i) {
+              val = cadd(val, cscale(0.5, cadd(grad_c(P, G, LD, c, i), grad_c(P, G, LD, i, c))));
+            } else {
+              const int pr = c < P.H ? c : c - P.H;
+              if ((P.diag_keep_mask >> pr) & 1) val = cadd(val, grad_c(P, G, LD, c, c));
+            }
           }
-        }
       const cd o = cmulj(gout, val);  // grad_out * conj(d lhaf / d A)
       lh_c128 r;
       r.re = o.r;
@@ -580,7 +625,8 @@ __global__ void scatter_dense_kernel(const Prob* __restrict__ probs, const cd* _
       dAb[(int64_t)x * lda + y] = r;
     } else {
       const int x = e - N * N;
-      for (int c = first[x]; c >= 0; c = nxt[c]) val = cadd(val, cscale(P.scale, G[LD * LD + c]));
+      if (P.n > 0)
+        for (int c = first[x]; c >= 0; c = nxt[c]) val = cadd(val, cscale(P.scale, G[LD * LD + c]));
       const cd o = cmulj(gout, val);
       lh_c128 r;
       r.re = o.r;
@@ -595,7 +641,7 @@ __global__ void scatter_dense_kernel(const Prob* __restrict__ probs, const cd* _
 __global__ void scatter_shared_kernel(const Prob* __restrict__ probs, int nprob,
                                       const int64_t* __restrict__ ioff,
                                       const int32_t* __restrict__ idx,
-                                      const cd* __restrict__ gslots,
+                                      const cd* __restrict__ grads,
                                       const lh_c128* __restrict__ grad_out, lh_c128* dA,
                                       int64_t lda, lh_c128* dg, int base_dim) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -606,7 +652,7 @@ __global__ void scatter_shared_kernel(const Prob* __restrict__ probs, int nprob,
     const Prob& P = probs[b];
     if (P.n == 0) continue;
     const int LD = 8 * P.B;
-    const cd* G = gslots + P.g_off;
+    const cd* G = grads + P.r_off;
     const int32_t* ib = idx ? idx + ioff[b] : nullptr;
     const lh_c128 go = grad_out[b];
     cd val = czero();

@@ -491,7 +491,7 @@ __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const 
       acci.hi = fma(coef, f.i, acci.hi);
     }
     sabs = fma(fabs(coef), sqrt(cabs2(f)), sabs);
-    if (saved && lane >= 1 && lane <= n) saved[P.s_off + t * n + (lane - 1)] = series_coef(L, n, lane);
+    if (saved && lane >= 1 && lane <= n) saved[P.s_off + (t - P.t0) * n + (lane - 1)] = series_coef(L, n, lane);
     wave_sync();
   }
   if (lane == 0) {
@@ -613,9 +613,10 @@ __attribute__((amdgpu_waves_per_eu(LH_FWD_WAVES(BMAX), LH_FWD_WAVES(BMAX)))) voi
 #ifdef LH_COMMON_KERNELS
 // Sum the item partials of each problem in item order (double-double),
 // apply the FDS prefactor and write the result and an error estimate.
+// With `raw` the prefactor is not applied (partial sums of a term range).
 __global__ void finalize_kernel(const Prob* __restrict__ probs, int nprob,
                                 const Partial* __restrict__ parts, lh_c128* out, lh_c128* out_lo,
-                                double* err, int acc_dd) {
+                                double* err, int acc_dd, int raw) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nprob) return;
   const Prob& P = probs[b];
@@ -631,7 +632,7 @@ __global__ void finalize_kernel(const Prob* __restrict__ probs, int nprob,
     dd_add(si, pr.hi, pr.li);
     sabs += pr.abs_sum;
   }
-  const double sc = P.scale;  // power of two: exact
+  const double sc = raw ? 1.0 : P.scale;  // power of two: exact
   sr.hi *= sc;
   sr.lo *= sc;
   si.hi *= sc;

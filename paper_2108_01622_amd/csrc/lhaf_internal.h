@@ -27,6 +27,8 @@ struct Prob {
   int32_t first_item, n_items;
   int32_t Nvert;  // rows of the problem's matrix (entries of its index list)
   int64_t g_off;  // backward: offset (lh_c128 units) of the item gradient slots
+  int64_t r_off;  // backward: offset of the problem's reduced gradient (LD^2 + 64 entries)
+                  // in the per-problem gradient layout
   int64_t s_off;  // offset of the problem's block in the per-term coefficient store
   int32_t diag_keep_mask;  // bit p set: pair p repeats (eta >= 2), keep C's diagonal
   double scale;   // 2^-n for scaled FDS, 1 otherwise

@@ -29,10 +29,11 @@ struct PersistArgs {
 template <int B>
 hipError_t launch_forward(const PersistArgs& a, const cd* ws, Partial* parts, int acc_dd,
                           cd* saved);
-// backward_kernel<B>: item gradient slots; per-wavefront scratch
+// backward_kernel<B>: item gradient slots; per-wavefront scratch; with
+// `parts` (fused pass) also the item partials of the value
 template <int B>
 hipError_t launch_backward(const PersistArgs& a, const cd* ws, cd* gslots, cd* scratch,
-                           const cd* saved);
+                           const cd* saved, Partial* parts, int acc_dd);
 // multi_kernel<B, MODE>: MODE 0 chain-rule outputs, 1 loop-weight vectors
 template <int B, int MODE>
 hipError_t launch_multi(const PersistArgs& a, const cd* ws, Partial* parts, int acc_dd,

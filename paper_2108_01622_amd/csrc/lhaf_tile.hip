@@ -52,10 +52,10 @@ template int resident_forward<LH_TILE>(size_t);
 #elif LH_FAMILY == 1
 template <int B>
 hipError_t launch_backward(const PersistArgs& a, const cd* ws, cd* gslots, cd* scratch,
-                           const cd* saved) {
+                           const cd* saved, Partial* parts, int acc_dd) {
   hipLaunchKernelGGL(HIP_KERNEL_NAME(backward_kernel<B>), dim3(a.grid), dim3(64), a.lds,
                      a.stream, a.probs, a.items, a.n_items, a.counter, ws, gslots, scratch, a.nmax,
-                     saved);
+                     saved, parts, acc_dd);
   return hipGetLastError();
 }
 template <int B>
@@ -66,7 +66,8 @@ int resident_backward(size_t lds) {
     return 0;
   return blocks;
 }
-template hipError_t launch_backward<LH_TILE>(const PersistArgs&, const cd*, cd*, cd*, const cd*);
+template hipError_t launch_backward<LH_TILE>(const PersistArgs&, const cd*, cd*, cd*, const cd*,
+                                              Partial*, int);
 template int resident_backward<LH_TILE>(size_t);
 #elif LH_FAMILY == 2
 template <int B, int MODE>

@@ -240,24 +240,168 @@ def test_saved_store_errors(T, api):
     small = T.empty(count - 1, dtype=T.complex128, device="cuda")
     with pytest.raises(LhafError, match="workspace too small"):
         api.lhaf_batched(At, gt, saved=small)
-    full = T.empty(count, dtype=T.complex128, device="cuda")
-    with pytest.raises(LhafError, match="unsupported"):
-        api.lhaf_batched(At, gt, saved=full, term_begin=0, term_end=5, scaled=False)
+    # a term range needs a store of that range only
+    assert api.lhaf_saved_count(np.array([0, 12]), term_begin=3, term_end=8) == 5 * 6
+    part = T.empty(5 * 6 - 1, dtype=T.complex128, device="cuda")
+    with pytest.raises(LhafError, match="workspace too small"):
+        api.lhaf_batched(At, gt, saved=part, term_begin=3, term_end=8, scaled=False)
     with pytest.raises(LhafError, match="workspace too small"):
         api.lhaf_backward(At, gt, T.ones(1, dtype=T.complex128, device="cuda"), saved=small)
 
 
-def test_autograd_with_and_without_store(T, api):
+def test_autograd_modes_agree(T, api):
+    """The three autograd modes (fused pass, recomputation, coefficient store)
+    give the same values and gradients to rounding."""
     rng = np.random.Generator(np.random.PCG64(31))
     mats = [I.gaussian_state_matrix(16, rng) for _ in range(3)]
     A = np.stack([m[0] for m in mats])
     g = np.stack([m[1] for m in mats])
     res = []
-    for frac in (0.5, 0.0):
+    for mode in ("fused", "store", "recompute"):
         At = dev(T, A).requires_grad_(True)
         gt = dev(T, g).requires_grad_(True)
-        out = api.lhaf_autograd(At, gt, store_fraction=frac)
+        out = api.lhaf_autograd(At, gt, mode=mode)
         (out * dev(T, np.array([1.0, -1j, 0.5]))).sum().real.backward()
-        res.append((At.grad.clone(), gt.grad.clone()))
-    for a, b in zip(res[0], res[1]):
-        assert float((a - b).abs().max()) <= 1e-12 * float(b.abs().max())
+        res.append((out.detach().clone(), At.grad.clone(), gt.grad.clone()))
+    for other in res[1:]:
+        for a, b in zip(res[0], other):
+            assert float((a - b).abs().max()) <= 1e-12 * float(b.abs().max())
+
+
+@pytest.mark.parametrize("mode", ["fds", "et"])
+@pytest.mark.parametrize("acc", ["dd", "fp64"])
+def test_fused_pass_matches_separate_passes(T, api, orc, mode, acc):
+    """The fused pass (values and per-problem gradients in one launch) against
+    lhaf_batched and lhaf_backward on a shared base with index lists of mixed
+    sizes (several tiles in one launch) and on a repeated pattern; the values
+    also against the oracle."""
+    base = I.state100(0)
+    Bm, gam = dev(T, base["B"]), dev(T, base["gamma"])
+    lists = [np.arange(0, 30, 2), np.arange(5, 41), np.array([3, 10, 99]), np.arange(60, 78)]
+    idx = np.concatenate(lists)
+    off = np.cumsum([0] + [len(x) for x in lists]).astype(np.int64)
+    go = dev(T, np.array([1.0, 0.5 - 0.25j, -2j, 0.75]))
+    grads = T.empty(api.lhaf_grads_count(off), dtype=T.complex128, device="cuda")
+    v_f, e_f = api.lhaf_batched(Bm, gam, idx=idx, idx_off=off, sum=mode, acc=acc, grads=grads,
+                                return_error=True)
+    v_s, e_s = api.lhaf_batched(Bm, gam, idx=idx, idx_off=off, sum=mode, acc=acc,
+                                return_error=True)
+    dA_f, dg_f = api.lhaf_backward(Bm, gam, go, idx=idx, idx_off=off, sum=mode, grads=grads)
+    dA_s, dg_s = api.lhaf_backward(Bm, gam, go, idx=idx, idx_off=off, sum=mode)
+    tol = 1e-12 if mode == "fds" else 1e-10
+    assert float((v_f - v_s).abs().max()) <= tol * float(v_s.abs().max())
+    assert float((dA_f - dA_s).abs().max()) <= tol * float(dA_s.abs().max())
+    assert float((dg_f - dg_s).abs().max()) <= tol * float(dg_s.abs().max())
+    vv = v_f.cpu().numpy()
+    for b in (0, 2):
+        ix = lists[b]
+        want = orc.lhaf_memo(base["B"][np.ix_(ix, ix)], base["gamma"][ix], prec="f128") \
+            if len(ix) <= 16 else None
+        if want is not None:
+            assert abs(vv[b] - want) <= max(1e-10 * abs(want), 4 * float(e_f[b])), b
+    # repeated rows, dense stack of one
+    A, g = I.random_symmetric(7, 777)
+    r = np.array([2, 1, 3, 0, 1, 2, 1], dtype=np.int32)
+    At, gt = dev(T, A)[None], dev(T, g)[None]
+    grads = T.empty(api.lhaf_grads_count(np.array([0, 7]), r), dtype=T.complex128, device="cuda")
+    v_f = api.lhaf_batched(At, gt, r=r, sum=mode, acc=acc, grads=grads)
+    want = orc.lhaf_memo(*orc.repeat_matrix(A, g, r), prec="f128")
+    assert abs(v_f.item() - want) <= 1e-10 * abs(want)
+    one = T.ones(1, dtype=T.complex128, device="cuda")
+    dA_f, dg_f = api.lhaf_backward(At, gt, one, r=r, sum=mode, grads=grads)
+    dA_s, dg_s = api.lhaf_backward(At, gt, one, r=r, sum=mode)
+    assert float((dA_f - dA_s).abs().max()) <= tol * float(dA_s.abs().max())
+    assert float((dg_f - dg_s).abs().max()) <= tol * float(dg_s.abs().max())
+
+
+def test_fused_pass_term_slices(T, api):
+    """Fused pass over term slices: raw value partials and gradient shares
+    add up to the full value and gradient."""
+    rng = np.random.Generator(np.random.PCG64(5151))
+    mats = [I.gaussian_state_matrix(18, rng) for _ in range(2)]
+    A = dev(T, np.stack([m[0] for m in mats]))
+    g = dev(T, np.stack([m[1] for m in mats]))
+    off = np.arange(3, dtype=np.int64) * 18
+    Tn = int(api.Bn.term_count(18))
+    go = dev(T, np.array([1.0, -1j]))
+    v_full = api.lhaf_batched(A, g)
+    dA_full, dg_full = api.lhaf_backward(A, g, go)
+    grads = T.empty(api.lhaf_grads_count(off), dtype=T.complex128, device="cuda")
+    vs = T.zeros_like(v_full)
+    sA, sg = T.zeros_like(dA_full), T.zeros_like(dg_full)
+    for a, b in ((0, 3), (3, Tn // 2), (Tn // 2, Tn)):
+        vs += api.lhaf_batched(A, g, term_begin=a, term_end=b, scaled=False, grads=grads)
+        pA, pg = api.lhaf_backward(A, g, go, grads=grads)
+        sA += pA
+        sg += pg
+    vs *= 2.0 ** -9
+    assert float((vs - v_full).abs().max()) <= 1e-12 * float(v_full.abs().max())
+    assert float((sA - dA_full).abs().max()) <= 1e-12 * float(dA_full.abs().max())
+    assert float((sg - dg_full).abs().max()) <= 1e-12 * float(dg_full.abs().max())
+
+
+@pytest.mark.parametrize("mode", ["fds", "et"])
+def test_backward_term_slices_add_up(T, api, mode):
+    """The gradient of disjoint term ranges covering all terms adds up to the
+    full gradient (each term is independent), with and without the store,
+    for a dense batch of mixed sizes and a shared base with index lists."""
+    rng = np.random.Generator(np.random.PCG64(5150))
+    mats = [I.gaussian_state_matrix(14, rng) for _ in range(3)]
+    A = np.stack([m[0] for m in mats])
+    g = np.stack([m[1] for m in mats])
+    At, gt = dev(T, A), dev(T, g)
+    go = dev(T, np.array([1.0, 0.25 - 1j, 2j]))
+    dA, dg = api.lhaf_backward(At, gt, go, sum=mode)
+    Tn = int(api.Bn.term_count(14, sum=mode))
+    cuts = [0, 1, 17, Tn // 2 + 5, Tn - 3, Tn]
+    assert cuts == sorted(cuts) and len(set(cuts)) == len(cuts)
+    off = np.arange(4, dtype=np.int64) * 14
+    sA, sg = T.zeros_like(dA), T.zeros_like(dg)
+    sA2, sg2 = T.zeros_like(dA), T.zeros_like(dg)
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        pA, pg = api.lhaf_backward(At, gt, go, sum=mode, term_begin=a, term_end=b)
+        sA += pA
+        sg += pg
+        store = T.empty(api.lhaf_saved_count(off, sum=mode, term_begin=a, term_end=b),
+                        dtype=T.complex128, device="cuda")
+        api.lhaf_batched(At, gt, sum=mode, term_begin=a, term_end=b, scaled=False, saved=store)
+        qA, qg = api.lhaf_backward(At, gt, go, sum=mode, term_begin=a, term_end=b, saved=store)
+        sA2 += qA
+        sg2 += qg
+    tol = 1e-12 if mode == "fds" else 1e-10
+    for x, y in ((sA, dA), (sg, dg), (sA2, dA), (sg2, dg)):
+        assert float((x - y).abs().max()) <= tol * float(y.abs().max())
+    # a range past the end contributes nothing
+    zA, zg = api.lhaf_backward(At, gt, go, sum=mode, term_begin=Tn, term_end=Tn + 5)
+    assert float(zA.abs().max()) == 0.0 and float(zg.abs().max()) == 0.0
+
+
+def test_dense_stack_with_index_lists(T, api, orc):
+    """A dense stack with index lists: problem b is the submatrix of A_b on
+    the rows idx_b (a permuted subset of fewer rows than A_b has).  Gradients
+    land on those rows of dA_b / dgamma_b; every other entry is 0."""
+    rng = np.random.Generator(np.random.PCG64(8080))
+    M = 12
+    mats = [I.random_symmetric(M, 8100 + b) for b in range(3)]
+    A = np.stack([m[0] for m in mats])
+    g = np.stack([m[1] for m in mats])
+    idx = [rng.permutation(M)[:k] for k in (9, 12, 7)]
+    off = np.array([0, 9, 21, 28], dtype=np.int64)
+    go = np.array([1.0, -0.5 + 1j, 0.75j])
+    dA, dg = api.lhaf_backward(dev(T, A), dev(T, g), dev(T, go), idx=np.concatenate(idx), idx_off=off)
+    dA, dg = dA.cpu().numpy(), dg.cpu().numpy()
+    for b in range(3):
+        ix = list(idx[b])
+        As, gs = A[b][np.ix_(ix, ix)], g[b][ix]
+        As = 0.5 * (As + As.T)
+        unused = sorted(set(range(M)) - set(ix))
+        for x in unused:
+            assert dg[b, x] == 0 and np.all(dA[b, x, :] == 0) and np.all(dA[b, :, x] == 0)
+        for k in (0, len(ix) - 1):
+            want = go[b] * np.conj(orc.lhaf_memo(*orc.remove(As, gs, [k]), prec="f128"))
+            assert rel(dg[b, ix[k]], want) < 1e-10, (b, k)
+        k, l = 1, len(ix) - 2
+        want = go[b] * np.conj(0.5 * orc.lhaf_memo(*orc.remove(As, gs, [k, l]), prec="f128"))
+        assert rel(dA[b, ix[k], ix[l]], want) < 1e-10
+        assert rel(dA[b, ix[l], ix[k]], want) < 1e-10
+        assert np.all(np.diag(dA[b]) == 0)
