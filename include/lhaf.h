@@ -60,6 +60,7 @@ typedef int32_t lh_status;
 #define LH_EHIP 3          /* a HIP runtime call failed */
 #define LH_ENOMEM 4        /* workspace too small / allocation failed */
 #define LH_EUNSUPPORTED 5  /* option combination not supported */
+#define LH_ESCRATCH 6      /* batch too large for lhaf_batched_noalloc's fixed scratch */
 
 #define LH_SUM_ET 0  /* eigenvalue-trace inclusion/exclusion (App. B.1/B.2) */
 #define LH_SUM_FDS 1 /* finite-difference sieve (App. B.4), sign-halved */
@@ -164,6 +165,27 @@ lh_status lhaf_batched(int32_t B, const lh_c128* A_base, int64_t lda, int64_t st
                        const lh_c128* gamma_base, int64_t stride_g, const int32_t* idx,
                        const int64_t* idx_off, const int32_t* r, lh_c128* out, double* err_est,
                        void* workspace, size_t ws_bytes, const lh_opts* opts, void* stream);
+
+/* lhaf_batched for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same problems, options, results and errors as lhaf_batched, with the
+ * workspace taken from a fixed device array inside the library instead of
+ * one the caller passes (opts->workspace is ignored).  The call makes no
+ * hipMalloc, hipFree, pinned-host or other device allocation; the plan
+ * tables are copied from pageable host memory.  The array holds
+ * lhaf_noalloc_scratch_bytes() bytes (64 MiB) on every GPU the library runs
+ * on, until the process ends; a batch whose workspace (lhaf_batched_workspace)
+ * exceeds it returns LH_ESCRATCH and queues nothing.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams or
+ * host threads, before the previous call's work has finished) race and give
+ * wrong results.  Calls queued one after another on the same stream are safe.
+ * The caller still owns A_base, gamma_base, idx, out, err_est and any
+ * opts->out_lo / opts->saved. */
+lh_status lhaf_batched_noalloc(int32_t B, const lh_c128* A_base, int64_t lda, int64_t stride_A,
+                               const lh_c128* gamma_base, int64_t stride_g, const int32_t* idx,
+                               const int64_t* idx_off, const int32_t* r, lh_c128* out,
+                               double* err_est, const lh_opts* opts, void* stream);
+size_t lhaf_noalloc_scratch_bytes(void);
 
 /* Mixed-state form lhafmix(A, gamma, n) (App. B.2): A is 2M x 2M (device,
  * lda >= 2M), gamma has 2M entries, n (HOST, M entries >= 0) gives the photon

@@ -75,6 +75,11 @@ def lib():
         L.lhaf_batched.argtypes = [i32, vp, i64, i64, vp, i64, vp, vp, vp, vp, vp, vp, sz,
                                    P(LhOpts), vp]
         L.lhaf_batched.restype = i32
+        L.lhaf_batched_noalloc.argtypes = [i32, vp, i64, i64, vp, i64, vp, vp, vp, vp, vp,
+                                           P(LhOpts), vp]
+        L.lhaf_batched_noalloc.restype = i32
+        L.lhaf_noalloc_scratch_bytes.argtypes = []
+        L.lhaf_noalloc_scratch_bytes.restype = sz
         L.lhaf_real.argtypes = [vp, i64, vp, vp, i32, vp, vp, P(LhOpts), vp]
         L.lhaf_real.restype = i32
         L.lhaf_mixed.argtypes = [vp, i64, vp, vp, i32, vp, vp, P(LhOpts), vp]
@@ -98,6 +103,7 @@ def lib():
 
 EXPORTED = ["lh_opts_default", "lh_status_string", "lhaf_schedule_count", "lhaf_term_count",
             "lhaf_plan_pairs", "lhaf", "lhaf_repeated", "lhaf_batched_workspace", "lhaf_batched",
+            "lhaf_batched_noalloc", "lhaf_noalloc_scratch_bytes",
             "lhaf_real", "lhaf_mixed", "lhaf_chain", "lhaf_gammas", "lhaf_saved_count", "lhaf_grads_count", "lhaf_backward_workspace",
             "lhaf_backward"]
 

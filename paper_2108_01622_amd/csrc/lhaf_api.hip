@@ -303,7 +303,7 @@ struct StageBuf {
   hipEvent_t done = nullptr;
   bool pending = false;
 };
-// Calls that must not allocate device or pinned memory stage
+// The entry point that allocates nothing (lhaf_batched_noalloc) stages
 // through a separate ring of pageable host buffers (std::vector, no pinned
 // or device allocation); the runtime copies those through its own staging.
 struct PageBuf {
@@ -439,6 +439,27 @@ lh_status run_forward(Plan& pl, const lh_c128* A, int64_t lda, const lh_c128* g,
   return LH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Fixed device workspace of lhaf_batched_noalloc: one array per GPU, part of
+// the library's code object, held until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in for
+// the symbol): the device address comes from hipGetSymbolAddress, taken once
+// per device with that device current, and is kept in g_static.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+static void* g_static[64] = {nullptr};
+
+lh_status static_scratch(int dev, void** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_static[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LH_EHIP;
+    g_static[dev] = ptr;
+  }
+  *out = g_static[dev];
+  return LH_OK;
+}
+
 }  // namespace lh
 
 // ===========================================================================
@@ -467,6 +488,7 @@ const char* lh_status_string(lh_status s) {
     case LH_EHIP: return "HIP runtime error";
     case LH_ENOMEM: return "workspace too small or allocation failed";
     case LH_EUNSUPPORTED: return "unsupported option combination";
+    case LH_ESCRATCH: return "batch needs more than the fixed device scratch of lhaf_batched_noalloc";
     default: return "unknown status";
   }
 }
@@ -636,6 +658,36 @@ lh_status lhaf_batched(int32_t B, const lh_c128* A_base, int64_t lda, int64_t st
   return batched_impl(B, A_base, lda, stride_A, gamma_base, stride_g, idx, idx_off, r, out,
                       err_est, workspace, ws_bytes, o, (hipStream_t)stream, false, nullptr);
 }
+
+lh_status lhaf_batched_noalloc(int32_t B, const lh_c128* A_base, int64_t lda, int64_t stride_A,
+                               const lh_c128* gamma_base, int64_t stride_g, const int32_t* idx,
+                               const int64_t* idx_off, const int32_t* r, lh_c128* out,
+                               double* err_est, const lh_opts* opts, void* stream) {
+  lh_opts o;
+  lh_status s = validate_opts(opts, o);
+  if (s != LH_OK) return s;
+  if (o.grads) return LH_EUNSUPPORTED;
+  std::vector<ProblemIn> pin;
+  s = parse_problems(B, idx_off, r, stride_A, stride_g, pin);
+  if (s != LH_OK) return s;
+  int dev = 0;
+  s = ensure_device(dev);
+  if (s != LH_OK) return s;
+  void* ptr = nullptr;
+  s = static_scratch(dev, &ptr);
+  if (s != LH_OK) return s;
+  Plan pl;
+  s = build_plan(pin, o, dev, pl, false);
+  if (s != LH_OK) return s;
+  if (pl.lay.total > kStaticScratchBytes) return LH_ESCRATCH;
+  if (o.saved && o.saved_count < pl.saved_need) return LH_ENOMEM;
+  if (B == 0) return LH_OK;
+  if (!A_base || !gamma_base || !out || lda < 1) return LH_EINVAL;
+  return run_forward(pl, A_base, lda, gamma_base, idx, out, err_est, o, ptr, (hipStream_t)stream,
+                     dev, true);
+}
+
+size_t lhaf_noalloc_scratch_bytes(void) { return kStaticScratchBytes; }
 
 lh_status lhaf(const lh_c128* A, int64_t lda, const lh_c128* gamma, int32_t N, lh_c128* out,
                double* err_est, const lh_opts* opts, void* stream) {
