@@ -33,7 +33,9 @@
  *     idx_off, opts) are read before the call returns.
  *   - Arguments are validated synchronously; a non-zero status means nothing
  *     was queued.  Results are valid after the stream is synchronised.
- *   - Non-finite inputs give a NaN result and err_est = +Inf.
+ *   - A non-finite entry that a problem reads (its matrix entries off the
+ *     diagonal, its loop weights; for repeated problems also A_ii) or an
+ *     overflow gives a NaN result and err_est = +Inf for that problem only.
  *   - The library keeps no state except one lazily created scratch buffer per
  *     device (used when opts->workspace is NULL) and the schedule cache read
  *     from $LHAF_TUNE_CACHE.  Calls on different streams of one device must

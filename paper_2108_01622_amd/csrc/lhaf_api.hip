@@ -167,13 +167,13 @@ struct Plan {
 };
 
 // wavefronts of one kernel instance resident per CU (occupancy query)
-int resident_per_cu(bool bwd, int bmax, int nmax) {
+int resident_per_cu(bool bwd, int bmax, int nmax, int et) {
   const size_t lds = bwd ? bwd_lds_bytes(bmax, std::max(nmax, 1)) : lds_bytes_for(std::max(nmax, 1));
   int blocks = 0;
   switch (bmax) {
 #define LH_FN(BB)                                                      \
   case BB:                                                             \
-    blocks = bwd ? resident_backward<BB>(lds) : resident_forward<BB>(lds); \
+    blocks = bwd ? resident_backward<BB>(lds) : resident_forward<BB>(lds, et); \
     break;
     LH_FN(1) LH_FN(2) LH_FN(3) LH_FN(4) LH_FN(5) LH_FN(6) LH_FN(7)
     default: LH_FN(8)
@@ -220,7 +220,8 @@ lh_status build_plan(std::vector<ProblemIn>& pin, const lh_opts& o, int dev, Pla
   const int sched = pick_schedule(&o, pl.bmax, mode_any);
   const Schedule S = kSchedules[sched];
   const int cus = g_dev[dev].cus;
-  const int waves = std::max(1, cus * resident_per_cu(for_backward, pl.bmax, pl.nmax));
+  const int waves =
+      std::max(1, cus * resident_per_cu(for_backward, pl.bmax, pl.nmax, o.sum == LH_SUM_ET));
   const double target = std::max(total_cost / ((double)waves * S.items_per_wave), 1e-9);
   struct Tmp {
     int prob;
@@ -424,7 +425,7 @@ lh_status run_forward(Plan& pl, const lh_c128* A, int64_t lda, const lh_c128* g,
     hipError_t e;
     switch (pl.bmax) {
 #define LH_FCASE(BB) \
-  case BB: e = launch_forward<BB>(pa, wsc, parts, acc_dd, sv); break;
+  case BB: e = launch_forward<BB>(pa, wsc, parts, acc_dd, sv, o.sum == LH_SUM_ET); break;
       LH_FCASE(1) LH_FCASE(2) LH_FCASE(3) LH_FCASE(4) LH_FCASE(5) LH_FCASE(6) LH_FCASE(7)
       default: LH_FCASE(8)
 #undef LH_FCASE

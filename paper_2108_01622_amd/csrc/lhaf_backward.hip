@@ -174,8 +174,21 @@ __device__ __forceinline__ void mul_right_dpp(double (&Rr)[B][B], double (&Ri)[B
     }
 }
 
-// row-group size per tile: bounded accumulator footprint
-__host__ __device__ constexpr int mul_group(int B) { return B; }
+// row-group size of the unstaged products: all row groups at once (M
+// streamed once) up to B = 7; one at a time at B = 8, where a second full
+// accumulator next to R does not fit the register file (measured: B = 7
+// 0.62 vs 0.49 M terms/s all-at-once vs one group, B = 8 0.09 vs 0.24)
+#ifndef LH_MULG
+#define LH_MULG(B) ((B) <= 7 ? (B) : 1)
+#endif
+// opaque lane index per term in the backward kernels of the unstaged tiles
+// (kernel BMAX >= 6; measured +7 % at B = 6, +16 % at B = 7, -3 % at
+// B = 5).  Decided per kernel, not per item: every item path of a kernel
+// shares its register allocation.
+#ifndef LH_BWD_OPAQUE
+#define LH_BWD_OPAQUE(unstaged) (unstaged)
+#endif
+__host__ __device__ constexpr int mul_group(int B) { return LH_MULG(B); }
 
 template <int B>
 __device__ __forceinline__ void mul_right(double (&Rr)[B][B], double (&Ri)[B][B],
@@ -256,23 +269,44 @@ __device__ __forceinline__ void rank_terms(double (&Rr)[B][B], double (&Ri)[B][B
     cd* bb = xb + 64 * (i & 1);
     bb[lane] = cadd(b0, b1);
     wave_sync();
-    cd beta[B], al[B];
-#pragma unroll
-    for (int a = 0; a < B; ++a) beta[a] = bb[8 * a + p];
+    cd al[B];
 #pragma unroll
     for (int k = 0; k < B; ++k) {
       const int c = 8 * k + q;
       const int pc = c < H ? c + H : c - H;
       al[k] = c < m ? cscale(dcol[k], bv[S * i + pc]) : czero();
     }
+    // small tiles load every beta first (the LDS latencies overlap); larger
+    // ones one row group at a time, so only its beta is live next to R
+    constexpr int NB = B <= 5 ? B : 1;
+    cd beta[NB];
+    if constexpr (B <= 5) {
 #pragma unroll
-    for (int a = 0; a < B; ++a)
+      for (int a = 0; a < B; ++a) beta[a] = bb[8 * a + p];
+    }
+#pragma unroll
+    for (int a = 0; a < B; ++a) {
+      const cd be = B <= 5 ? beta[a < NB ? a : 0] : bb[8 * a + p];
 #pragma unroll
       for (int k = 0; k < B; ++k) {
-        const cd o = cfma(beta[a], al[k], mk(Rr[a][k], Ri[a][k]));
+        const cd o = cfma(be, al[k], mk(Rr[a][k], Ri[a][k]));
         Rr[a][k] = o.r;
         Ri[a][k] = o.i;
       }
+    }
+  }
+}
+
+// d of the pairs of the lane's rows i = 8a+p (0 beyond m)
+template <int B>
+__device__ __forceinline__ void row_weights(const double wl, const int m, const int H, const int p,
+                                            double (&drow)[B]) {
+#pragma unroll
+  for (int a = 0; a < B; ++a) {
+    const int i = 8 * a + p;
+    const int pi = i < H ? i : i - H;
+    const double d = shfl_d(wl, pi & 63);
+    drow[a] = i < m ? d : 0.0;
   }
 }
 
@@ -352,20 +386,21 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
                                              Partial* __restrict__ part, const int acc_dd) {
   constexpr int LD = 8 * B;
   constexpr int S = kStage ? LD : 64;    // stride of the Krylov vectors
-  const int lane = threadIdx.x & 63;
-  const int p = lane >> 3, q = lane & 7;
+  const int lane0 = threadIdx.x & 63;
   const int m = P.m, H = P.H, n = P.n;
   cd* pw = scr;                                          // [kMaxPS][LD*LD] powers
   cd* X = lds_x(L);                                      // staging region (kStage)
   cd* bv = kStage ? X : scr + kMaxPS * LD * LD;          // Krylov vectors
   cd* acoef = L.wb;                                      // a_1..a_n (index k)
 
-  // zero the item's accumulators
+  // The item's gradient accumulators: d f / d v in one register per lane,
+  // the matrix part in the item's slot (a register copy next to the products
+  // spills: measured 1.2 KB/lane at B = 5).
+  cd gv = czero();
 #pragma unroll
   for (int a = 0; a < B; ++a)
 #pragma unroll
-    for (int k = 0; k < B; ++k) G[(8 * a + p) * LD + 8 * k + q] = czero();
-  G[LD * LD + lane] = czero();
+    for (int k = 0; k < B; ++k) G[(8 * a + (lane0 >> 3)) * LD + 8 * k + (lane0 & 7)] = czero();
 
   int s = 1;
   while (s * s < n) ++s;
@@ -373,8 +408,12 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
   dd accr = {0.0, 0.0}, acci = {0.0, 0.0};
   double sabs = 0.0;
 
-  TermIter it = term_begin(P, t0, lane);
+  TermIter it = term_begin(P, t0, lane0);
   for (int64_t t = t0; t < t1; ++t) {
+    // lane index of this term (opaque for large tiles, see LH_BWD_OPAQUE)
+    int lane = lane0;
+    LH_OPAQUE(LH_BWD_OPAQUE(!kStage), lane);
+    const int p = lane >> 3, q = lane & 7;
     if (t != t0) term_next(it, H, lane);
     double coef;
     bool empty;
@@ -383,14 +422,14 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
       lane_sync<kStage>();
       continue;
     }
-    double dcol[B], drow[B];
-    column_weights<B>(wl, m, H, q, dcol);
-#pragma unroll
-    for (int a = 0; a < B; ++a) {
-      const int i = 8 * a + p;
-      const int pi = i < H ? i : i - H;
-      const double d = shfl_d(wl, pi & 63);
-      drow[a] = i < m ? d : 0.0;
+    // The pair weights of the lane's rows and columns: held through the term
+    // for the LDS-staged tiles, re-derived from wl (one value per lane) at
+    // each use for the larger ones, where they would sit next to the
+    // matrices in the register file.
+    double dcol_k[B], drow_k[B];
+    if constexpr (kStage) {
+      column_weights<B>(wl, m, H, q, dcol_k);
+      row_weights<B>(wl, m, H, p, drow_k);
     }
     const int lpair = lane < H ? lane : lane - H;
     const double dsh = shfl_d(wl, lpair & 63);
@@ -399,7 +438,13 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
     cd asaved = czero();
     if (saved && lane >= 1 && lane <= n) asaved = saved[P.s_off + (t - P.t0) * n + (lane - 1)];
     double Wr[B][B], Wi[B][B];
-    load_w<B>(Cp, dcol, p, q, Wr, Wi);
+    if constexpr (kStage) {
+      load_w<B>(Cp, dcol_k, p, q, Wr, Wi);
+    } else {
+      double dcol[B];
+      column_weights<B>(wl, m, H, q, dcol);
+      load_w<B>(Cp, dcol, p, q, Wr, Wi);
+    }
     krylov_b<B, S, kStage>(Wr, Wi, dlane, vp, m, H, n, p, q, lane, bv, L, saved == nullptr);
     if (saved) {
       if (lane >= 1 && lane <= n) acoef[lane] = asaved;
@@ -429,8 +474,20 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
     for (int a = 0; a < B; ++a)
 #pragma unroll
       for (int k = 0; k < B; ++k) Rr[a][k] = Ri[a][k] = 0.0;
-    rank_terms<B, S>(Rr, Ri, bv, acoef, dcol, m, H, n, p, q, lane, L.xb);
-    accumulate_g<B>(G, coef, drow, Rr, Ri, p, q);
+    if constexpr (kStage) {
+      rank_terms<B, S>(Rr, Ri, bv, acoef, dcol_k, m, H, n, p, q, lane, L.xb);
+    } else {
+      double dcol[B];
+      column_weights<B>(wl, m, H, q, dcol);
+      rank_terms<B, S>(Rr, Ri, bv, acoef, dcol, m, H, n, p, q, lane, L.xb);
+    }
+    if constexpr (kStage) {
+      accumulate_g<B>(G, coef, drow_k, Rr, Ri, p, q);
+    } else {
+      double drow[B];
+      row_weights<B>(wl, m, H, p, drow);
+      accumulate_g<B>(G, coef, drow, Rr, Ri, p, q);
+    }
     // ---- d f / d v_l = sum_k a_k (alpha_{k-1}[l] + d_{pair(l)} b_{k-1}[partner(l)])
     //                  = 2 sum_k a_k d_{pair(l)} b_{k-1}[partner(l)]
     if (lane < m) {
@@ -442,7 +499,7 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
         g1 = cfma(acoef[k + 1], bv[S * k + pl], g1);
       }
       if (k <= n) g0 = cfma(acoef[k], bv[S * (k - 1) + pl], g0);
-      G[LD * LD + lane] = cfma(mk(2.0 * coef * dlane, 0.0), cadd(g0, g1), G[LD * LD + lane]);
+      gv = cfma(mk(2.0 * coef * dlane, 0.0), cadd(g0, g1), gv);
     }
     lane_sync<kStage>();
 
@@ -450,7 +507,13 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
     // re-read from L2 (the pointer is hidden from the optimiser so it does
     // not keep the first copy live through the Hessenberg phase).
     const cd* Cp2 = launder_ptr(Cp);
-    load_w<B>(Cp2, dcol, p, q, Rr, Ri);
+    if constexpr (kStage) {
+      load_w<B>(Cp2, dcol_k, p, q, Rr, Ri);
+    } else {
+      double dcol[B];
+      column_weights<B>(wl, m, H, q, dcol);
+      load_w<B>(Cp2, dcol, p, q, Rr, Ri);
+    }
     if (kStage) store_mat<B>(Rr, Ri, X, p, q);
     if (s > 1) store_mat<B>(Rr, Ri, pw, p, q);  // W^1
     lane_sync<kStage>();
@@ -477,10 +540,17 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
         combine_powers<B>(Rr, Ri, false, pw, acoef, Q - 1 - (step - (s - 1)), s, n, m, p, q);
       }
     }
-    accumulate_g<B>(G, coef, drow, Rr, Ri, p, q);
+    if constexpr (kStage) {
+      accumulate_g<B>(G, coef, drow_k, Rr, Ri, p, q);
+    } else {
+      double drow[B];
+      row_weights<B>(wl, m, H, p, drow);
+      accumulate_g<B>(G, coef, drow, Rr, Ri, p, q);
+    }
     lane_sync<kStage>();
   }
-  if (part && lane == 0) {
+  G[LD * LD + lane0] = gv;
+  if (part && lane0 == 0) {
     Partial pr;
     pr.hr = accr.hi;
     pr.hi = acci.hi;

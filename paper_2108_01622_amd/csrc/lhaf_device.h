@@ -24,6 +24,22 @@ constexpr BinomTable make_binom_table() {
 }
 static __constant__ BinomTable c_binom = make_binom_table();
 
+// Opaque copies of the lane index.  Enabled, the persistent loops re-derive
+// every per-lane address and mask once per term (LH_OPAQUE_TERM) or per
+// Hessenberg step (LH_OPAQUE_STEP) instead of letting the compiler hoist them
+// into registers held for the whole kernel: fewer registers, more
+// instructions.  Off by default (measured faster where the hoisted values fit).
+#ifndef LH_OPAQUE_TERM
+#define LH_OPAQUE_TERM 0
+#endif
+#ifndef LH_OPAQUE_STEP
+#define LH_OPAQUE_STEP 0
+#endif
+#define LH_OPAQUE(flag, v)              \
+  do {                                  \
+    if (flag) asm volatile("" : "+v"(v)); \
+  } while (0)
+
 struct cd {
   double r, i;
 };
@@ -161,9 +177,9 @@ __device__ __forceinline__ double bcast0_d(double x) {
 }
 __device__ __forceinline__ cd bcast0(cd a) { return mk(bcast0_d(a.r), bcast0_d(a.i)); }
 
-// product over all 64 lanes (exact for the integer factors used here)
-__device__ __forceinline__ double prod_wave(double x) {
-  const int lane = threadIdx.x & 63;
+// product over all 64 lanes (exact for the integer factors used here); lane
+// is the caller's lane index (0..63)
+__device__ __forceinline__ double prod_wave(double x, const int lane) {
 #pragma unroll
   for (int s = 1; s < 64; s <<= 1) x *= shfl_d(x, lane ^ s);
   return x;

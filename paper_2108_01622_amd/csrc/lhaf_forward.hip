@@ -240,8 +240,12 @@ struct HessLoop {
     for (int jj = 0; jj < 8; ++jj) {
       const int j = 8 * KB + jj;
       if (j >= m) return;
-      if (j <= m - 3) householder_step<B, KB>(Wr, Wi, jj, j, p, q, L);
-      charpoly_step<B, KB>(Wr, Wi, jj, j, p, q, lane, n, pi, hsub, L);
+      // lane index of this step (optionally opaque, see LH_OPAQUE_STEP)
+      int ln = lane;
+      LH_OPAQUE(LH_OPAQUE_STEP, ln);
+      const int pp = ln >> 3, qq = ln & 7;
+      if (j <= m - 3) householder_step<B, KB>(Wr, Wi, jj, j, pp, qq, L);
+      charpoly_step<B, KB>(Wr, Wi, jj, j, pp, qq, ln, n, pi, hsub, L);
     }
     HessLoop<B, KB + 1>::run(Wr, Wi, m, n, p, q, lane, pi, hsub, L);
   }
@@ -300,7 +304,7 @@ __device__ __forceinline__ double term_weight(const TermIter& it, const Prob& P,
     wl = 0.0;
     fl = 1.0;
   }
-  coef = prod_wave(fl);
+  coef = prod_wave(fl, lane);
   empty = !fds && __ballot(lane < P.H && it.digit != 0) == 0ull;
   return wl;
 }
@@ -450,21 +454,120 @@ __device__ __forceinline__ cd series_coef(const LdsView& L, const int n, const i
 }
 
 // -------------------------------------------------------------------------
+// ET pair deletion (App. B.2): a pair with weight z_p = 0 contributes zero
+// columns to W = C X_z and a zero entry to u = X_z v, so the term's traces
+// and loop moments are those of the reduced problem on the kept pairs, with
+// m = 2 H' (H' kept pairs) and the same lambda degree n.  km receives the
+// full-problem position of every reduced position -- kept pairs' first ends
+// in pair order, then their partners -- and -1 beyond 2 H'.  Returns H'.
+__device__ __forceinline__ int kept_map(const TermIter& it, const int H, const int lane,
+                                        int* __restrict__ km) {
+  const bool kept = lane < H && it.digit != 0;
+  const unsigned long long keep = __ballot(kept);
+  const int Hk = __popcll(keep);
+  if (kept) {
+    const int r = __popcll(keep & ((1ull << lane) - 1ull));
+    km[r] = lane;
+    km[Hk + r] = H + lane;
+  }
+  if (lane >= 2 * Hk) km[lane] = -1;
+  wave_sync();
+  return Hk;
+}
+
+// One term at register tile b: W = C X (every pair, or through km only the
+// kept pairs of an ET term), loop moments and the two series into L.ser;
+// returns f = [lambda^n] of the product of the series on every lane.
+template <int b>
+__device__ __forceinline__ cd term_f(const cd* __restrict__ Cp, const int LDp,
+                                     const cd* __restrict__ vp, const int* __restrict__ km,
+                                     const double wl, const int mt, const int Ht, const int H,
+                                     const int n, const int p, const int q, const int lane,
+                                     LdsView& L) {
+  double dcol[b];
+  double Wr[b][b], Wi[b][b];
+  if (km) {
+    int oc[b];
+#pragma unroll
+    for (int k = 0; k < b; ++k) {
+      const int c = 8 * k + q;
+      oc[k] = c < mt ? km[c] : -1;
+      const int pr = oc[k] < 0 ? 0 : (oc[k] < H ? oc[k] : oc[k] - H);
+      const double d = shfl_d(wl, pr & 63);
+      dcol[k] = oc[k] >= 0 ? d : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < b; ++a) {
+      const int i = 8 * a + p;
+      const int oi = i < mt ? km[i] : -1;
+#pragma unroll
+      for (int k = 0; k < b; ++k) {
+        cd c = czero();
+        if (oi >= 0 && oc[k] >= 0) c = Cp[oi * LDp + oc[k]];
+        Wr[a][k] = c.r * dcol[k];
+        Wi[a][k] = c.i * dcol[k];
+      }
+    }
+  } else {
+    column_weights<b>(wl, mt, Ht, q, dcol);
+    load_w<b>(Cp, dcol, p, q, Wr, Wi);
+  }
+  loop_moments<b>(Wr, Wi, dcol, vp, mt, Ht, n, p, q, lane, L);
+  spectral_series<b>(Wr, Wi, mt, n, p, q, lane, L);
+  // f = sum_k q_k L_{n-k}: lanes over k, full-wave sum (every lane gets f)
+  cd f = czero();
+  if (lane <= n) f = cmul(L.ser[lane], L.ser[33 + n - lane]);
+  return mk(sum_col8(sum_row8(f.r)), sum_col8(sum_row8(f.i)));
+}
+
+// term_f at the runtime tile bt (1 <= bt <= BMAX; uniform over the wavefront)
+template <int BMAX>
+__device__ __forceinline__ cd term_f_at(const int bt, const cd* __restrict__ Cp, const int LDp,
+                                        const cd* __restrict__ vp, const int* __restrict__ km,
+                                        const double wl, const int mt, const int Ht, const int H,
+                                        const int n, const int p, const int q, const int lane,
+                                        LdsView& L) {
+  cd f = czero();
+  switch (bt) {
+#define LH_TCASE(BB)                                                                 \
+  case BB:                                                                           \
+    if constexpr (BB <= BMAX)                                                        \
+      f = term_f<BB>(Cp, LDp, vp, km, wl, mt, Ht, H, n, p, q, lane, L);              \
+    break;
+    LH_TCASE(1) LH_TCASE(2) LH_TCASE(3) LH_TCASE(4) LH_TCASE(5) LH_TCASE(6) LH_TCASE(7)
+    LH_TCASE(8)
+#undef LH_TCASE
+    default:
+      break;
+  }
+  return f;
+}
+
+// -------------------------------------------------------------------------
 // Evaluate terms [t0, t1) of problem P; writes the item's partial sum (and,
-// with a coefficient store, the a_k of every term).
-template <int B>
+// with a coefficient store, the a_k of every term).  kET: an ET batch, whose
+// terms run on their kept pairs only, at tile ceil(2H'/8) <= B chosen per
+// term; otherwise every term runs at the problem's tile B = P.B.  (ET and
+// FDS batches are separate kernels: the per-term tile switch would raise the
+// register pressure of the FDS path.)
+template <int B, bool kET>
 __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const int64_t t1,
                                          const cd* __restrict__ Cp, const cd* __restrict__ vp,
                                          Partial* __restrict__ out, LdsView& L, const int acc_dd,
                                          cd* __restrict__ saved) {
-  const int lane = threadIdx.x & 63;
-  const int p = lane >> 3, q = lane & 7;
-  const int m = P.m, H = P.H, n = P.n;
-  TermIter it = term_begin(P, t0, lane);
+  const int lane0 = threadIdx.x & 63;
+  const int m = P.m, H = P.H, n = P.n, LDp = 8 * P.B;
+  int* km = reinterpret_cast<int*>(L.wv);  // free until the Hessenberg phase
+  cd* vred = L.xb + 64;                    // overwritten only after loop_moments read it
+  TermIter it = term_begin(P, t0, lane0);
   dd accr = {0.0, 0.0}, acci = {0.0, 0.0};
   double sabs = 0.0;
 
   for (int64_t t = t0; t < t1; ++t) {
+    // lane index of this term (optionally opaque, see LH_OPAQUE_TERM)
+    int lane = lane0;
+    LH_OPAQUE(LH_OPAQUE_TERM, lane);
+    const int p = lane >> 3, q = lane & 7;
     if (t != t0) term_next(it, H, lane);
     double coef;
     bool empty;
@@ -473,16 +576,16 @@ __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const 
       wave_sync();
       continue;
     }
-    double dcol[B];
-    column_weights<B>(wl, m, H, q, dcol);
-    double Wr[B][B], Wi[B][B];
-    load_w<B>(Cp, dcol, p, q, Wr, Wi);
-    loop_moments<B>(Wr, Wi, dcol, vp, m, H, n, p, q, lane, L);
-    spectral_series<B>(Wr, Wi, m, n, p, q, lane, L);
-    // f = sum_k q_k L_{n-k}: lanes over k, full-wave sum (every lane gets f)
-    cd f = czero();
-    if (lane <= n) f = cmul(L.ser[lane], L.ser[33 + n - lane]);
-    f = mk(sum_col8(sum_row8(f.r)), sum_col8(sum_row8(f.i)));
+    cd f;
+    if constexpr (kET) {
+      const int Hk = kept_map(it, H, lane, km);
+      const int mk_ = 2 * Hk;
+      vred[lane] = lane < mk_ ? vp[km[lane]] : czero();
+      wave_sync();
+      f = term_f_at<B>((mk_ + 7) >> 3, Cp, LDp, vred, km, wl, mk_, Hk, H, n, p, q, lane, L);
+    } else {
+      f = term_f<B>(Cp, LDp, vp, nullptr, wl, m, H, H, n, p, q, lane, L);
+    }
     if (acc_dd) {
       dd_add_prod(accr, coef, f.r);
       dd_add_prod(acci, coef, f.i);
@@ -494,7 +597,7 @@ __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const 
     if (saved && lane >= 1 && lane <= n) saved[P.s_off + (t - P.t0) * n + (lane - 1)] = series_coef(L, n, lane);
     wave_sync();
   }
-  if (lane == 0) {
+  if (lane0 == 0) {
     Partial pr;
     pr.hr = accr.hi;
     pr.hi = acci.hi;
@@ -568,7 +671,7 @@ __global__ void pack_kernel(const Prob* __restrict__ probs, const int64_t* __res
 #define LH_FWD_WAVES(bmax) ((bmax) <= 3 ? 4 : ((bmax) <= 4 ? 3 : ((bmax) <= 6 ? 2 : 1)))
 #endif
 
-template <int BMAX>
+template <int BMAX, bool kET>
 __global__ __launch_bounds__(64)
 __attribute__((amdgpu_waves_per_eu(LH_FWD_WAVES(BMAX), LH_FWD_WAVES(BMAX)))) void forward_kernel(const Prob* __restrict__ probs,
                                                      const Item* __restrict__ items, int n_items,
@@ -590,22 +693,20 @@ __attribute__((amdgpu_waves_per_eu(LH_FWD_WAVES(BMAX), LH_FWD_WAVES(BMAX)))) voi
     const int LD = 8 * P.B;
     const cd* Cp = ws + P.c_off;
     const cd* vp = Cp + LD * LD;
-    switch (P.B) {
-#define LH_CASE(BB)                                                     \
-  case BB:                                                              \
-    if (BB <= BMAX) run_item<(BB <= BMAX ? BB : 1)>(P, I.t0, I.t1, Cp, vp, parts + I.pad, L, acc_dd, saved); \
+    if constexpr (kET) {
+      if (P.B <= BMAX) run_item<BMAX, true>(P, I.t0, I.t1, Cp, vp, parts + I.pad, L, acc_dd, saved);
+    } else {
+      switch (P.B) {
+#define LH_CASE(BB)                                                                       \
+  case BB:                                                                                \
+    if constexpr (BB <= BMAX)                                                             \
+      run_item<BB, false>(P, I.t0, I.t1, Cp, vp, parts + I.pad, L, acc_dd, saved);        \
     break;
-      LH_CASE(1)
-      LH_CASE(2)
-      LH_CASE(3)
-      LH_CASE(4)
-      LH_CASE(5)
-      LH_CASE(6)
-      LH_CASE(7)
-      LH_CASE(8)
+        LH_CASE(1) LH_CASE(2) LH_CASE(3) LH_CASE(4) LH_CASE(5) LH_CASE(6) LH_CASE(7) LH_CASE(8)
 #undef LH_CASE
-      default:
-        break;
+        default:
+          break;
+      }
     }
   }
 }
@@ -638,6 +739,10 @@ __global__ void finalize_kernel(const Prob* __restrict__ probs, int nprob,
   si.hi *= sc;
   si.lo *= sc;
   sabs *= sc;
+  // a non-finite input (an entry the problem reads) or an overflow makes the
+  // whole result NaN, with err_est = +Inf
+  const bool bad = !isfinite(sr.hi + sr.lo) || !isfinite(si.hi + si.lo) || !isfinite(sabs);
+  if (bad) sr.hi = si.hi = sr.lo = si.lo = NAN;
   lh_c128 o;
   if (out_lo) {
     o.re = sr.hi;
@@ -658,7 +763,7 @@ __global__ void finalize_kernel(const Prob* __restrict__ probs, int nprob,
     double rel_term = 4.0 * (P.m + 1) * eps;
     if (!acc_dd) rel_term += (double)(P.t1 - P.t0) * eps;
     double e = sabs * rel_term;
-    if (!isfinite(o.re) || !isfinite(o.im) || !isfinite(e)) e = INFINITY;
+    if (bad || !isfinite(e)) e = INFINITY;
     err[b] = e;
   }
 }

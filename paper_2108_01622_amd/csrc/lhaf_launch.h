@@ -25,10 +25,11 @@ struct PersistArgs {
   hipStream_t stream;
 };
 
-// forward_kernel<B>: item partials (and the per-term coefficient store)
+// forward_kernel<B, et>: item partials (and the per-term coefficient store);
+// et selects the ET instance (per-term tiles with pair deletion)
 template <int B>
 hipError_t launch_forward(const PersistArgs& a, const cd* ws, Partial* parts, int acc_dd,
-                          cd* saved);
+                          cd* saved, int et);
 // backward_kernel<B>: item gradient slots; per-wavefront scratch; with
 // `parts` (fused pass) also the item partials of the value
 template <int B>
@@ -45,7 +46,7 @@ hipError_t launch_real(const PersistArgs& a, const double* ws, Partial* parts, i
 // Resident workgroups per CU of one instance with `lds` bytes of dynamic LDS
 // (occupancy query of the runtime; 0 if the query fails).
 template <int B>
-int resident_forward(size_t lds);
+int resident_forward(size_t lds, int et);
 template <int B>
 int resident_backward(size_t lds);
 

@@ -57,15 +57,18 @@ __device__ __forceinline__ void run_item_multi(const Prob& P, const int64_t t0, 
                                                const cd* __restrict__ vp,
                                                Partial* __restrict__ out, LdsView& L,
                                                const int acc_dd, const MultiArgs& ma) {
-  const int lane = threadIdx.x & 63;
-  const int p = lane >> 3, q = lane & 7;
+  const int lane0 = threadIdx.x & 63;
   const int m = P.m, H = P.H, n = P.n;
   cd* Lbuf = lds_multi(L);   // gamma: [nout + 1][33] exponential series
   cd* mu2 = Lbuf + 33 * (ma.nout + 1);  // second moment buffer
-  TermIter it = term_begin(P, t0, lane);
+  TermIter it = term_begin(P, t0, lane0);
   dd accr = {0.0, 0.0}, acci = {0.0, 0.0};  // lane o: output o
   double sabs = 0.0;
   for (int64_t t = t0; t < t1; ++t) {
+    // lane index of this term (optionally opaque, see LH_OPAQUE_TERM)
+    int lane = lane0;
+    LH_OPAQUE(LH_OPAQUE_TERM, lane);
+    const int p = lane >> 3, q = lane & 7;
     if (t != t0) term_next(it, H, lane);
     double coef;
     bool empty;
@@ -74,11 +77,11 @@ __device__ __forceinline__ void run_item_multi(const Prob& P, const int64_t t0, 
       wave_sync();
       continue;
     }
-    double dcol[B];
-    column_weights<B>(wl, m, H, q, dcol);
-    double Wr[B][B], Wi[B][B];
-    load_w<B>(Cp, dcol, p, q, Wr, Wi);
     if constexpr (MODE == 1) {
+      double dcol[B];
+      column_weights<B>(wl, m, H, q, dcol);
+      double Wr[B][B], Wi[B][B];
+      load_w<B>(Cp, dcol, p, q, Wr, Wi);
       // loop moments of every vector (W intact), exponential series two at a time
       for (int g = 0; g < ma.nout; g += 2) {
         LdsView La = L;
@@ -105,13 +108,20 @@ __device__ __forceinline__ void run_item_multi(const Prob& P, const int64_t t0, 
         acc_term(accr, acci, sabs, coef, cadd(f0, f1), acc_dd);
       }
     } else {
-      loop_moments<B>(Wr, Wi, dcol, vp, m, H, n, p, q, lane, L);
-      spectral_series<B>(Wr, Wi, m, n, p, q, lane, L);  // q in ser[0..], L in ser[33..]
+      // chain outputs are ET sums: the term runs on its kept pairs only
+      // (tile ceil(2H'/8) <= B), see kept_map; the series land in L.ser
+      int* km = reinterpret_cast<int*>(L.wv);
+      cd* vred = L.xb + 64;
+      const int Hk = kept_map(it, H, lane, km);
+      const int mk_ = 2 * Hk;
+      vred[lane] = lane < mk_ ? vp[km[lane]] : czero();
+      wave_sync();
+      (void)term_f_at<B>((mk_ + 7) >> 3, Cp, 8 * P.B, vred, km, wl, mk_, Hk, H, n, p, q, lane, L);
       const int zbb = ma.pbb >= 0 ? __builtin_amdgcn_readlane(it.digit, ma.pbb) : 0;
       const int zbp = ma.pbp >= 0 ? __builtin_amdgcn_readlane(it.digit, ma.pbp) : 0;
       // binomial weights of the fixed pairs, parity of sum z
       const bool fixed = lane < H && lane != ma.pbb && lane != ma.pbp;
-      const double cf = prod_wave(fixed ? c_binom.v[it.eta_l][it.digit] : 1.0);
+      const double cf = prod_wave(fixed ? c_binom.v[it.eta_l][it.digit] : 1.0, lane);
       const int zpar = __popcll(__ballot(lane < H && (it.digit & 1))) & 1;
       if (lane < ma.nout) {
         const int jk = lane >> 1, ok = lane & 1;
@@ -132,7 +142,7 @@ __device__ __forceinline__ void run_item_multi(const Prob& P, const int64_t t0, 
     }
     wave_sync();
   }
-  if (lane < ma.nout) {
+  if (lane0 < ma.nout) {
     Partial pr;
     pr.hr = accr.hi;
     pr.hi = acci.hi;
@@ -140,7 +150,7 @@ __device__ __forceinline__ void run_item_multi(const Prob& P, const int64_t t0, 
     pr.li = acci.lo;
     pr.abs_sum = sabs;
     pr.pad0 = pr.pad1 = pr.pad2 = 0.0;
-    out[lane] = pr;
+    out[lane0] = pr;
   }
 }
 
@@ -162,22 +172,26 @@ __attribute__((amdgpu_waves_per_eu(LH_FWD_WAVES(BMAX), LH_FWD_WAVES(BMAX)))) voi
     const cd* Cp = ws + P.c_off;
     const cd* vp = Cp + LD * LD;
     Partial* out = parts + (int64_t)I.pad * ma.nout;
-    switch (P.B) {
+    if constexpr (MODE == 0) {  // per-term tiles inside (pair deletion)
+      if (P.B <= BMAX) run_item_multi<BMAX, 0>(P, I.t0, I.t1, Cp, vp, out, L, acc_dd, ma);
+    } else {
+      switch (P.B) {
 #define LH_MCASE(BB)                                                                        \
   case BB:                                                                                  \
     if (BB <= BMAX) run_item_multi<(BB <= BMAX ? BB : 1), MODE>(P, I.t0, I.t1, Cp, vp, out, L, acc_dd, ma); \
     break;
-      LH_MCASE(1)
-      LH_MCASE(2)
-      LH_MCASE(3)
-      LH_MCASE(4)
-      LH_MCASE(5)
-      LH_MCASE(6)
-      LH_MCASE(7)
-      LH_MCASE(8)
+        LH_MCASE(1)
+        LH_MCASE(2)
+        LH_MCASE(3)
+        LH_MCASE(4)
+        LH_MCASE(5)
+        LH_MCASE(6)
+        LH_MCASE(7)
+        LH_MCASE(8)
 #undef LH_MCASE
-      default:
-        break;
+        default:
+          break;
+      }
     }
   }
 }
@@ -227,13 +241,15 @@ __global__ void finalize_multi_kernel(const Prob* __restrict__ probs,
   lh_c128 r;
   r.re = (sr.hi + sr.lo) * sc;
   r.im = (si.hi + si.lo) * sc;
+  const bool bad = !isfinite(r.re) || !isfinite(r.im) || !isfinite(sabs);
+  if (bad) r.re = r.im = NAN;  // non-finite input or overflow
   out[o] = r;
   if (err) {
     const double eps = 1.1102230246251565e-16;
     double rel_term = 4.0 * (P.m + 1) * eps;
     if (!acc_dd) rel_term += (double)(P.t1 - P.t0) * eps;
     double e = sabs * sc * rel_term;
-    if (!isfinite(r.re) || !isfinite(r.im) || !isfinite(e)) e = INFINITY;
+    if (bad || !isfinite(e)) e = INFINITY;
     err[o] = e;
   }
 }

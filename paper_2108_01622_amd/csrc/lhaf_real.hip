@@ -186,8 +186,11 @@ struct HessLoop {
     for (int jj = 0; jj < 8; ++jj) {
       const int j = 8 * KB + jj;
       if (j >= m) return;
-      if (j <= m - 3) householder_step<B, KB>(W, jj, j, p, q, L);
-      charpoly_step<B, KB>(W, jj, j, p, q, lane, n, pi, hsub, L);
+      int ln = lane;  // optionally opaque per step, as in the complex kernel
+      LH_OPAQUE(LH_OPAQUE_STEP, ln);
+      const int pp = ln >> 3, qq = ln & 7;
+      if (j <= m - 3) householder_step<B, KB>(W, jj, j, pp, qq, L);
+      charpoly_step<B, KB>(W, jj, j, pp, qq, ln, n, pi, hsub, L);
     }
     HessLoop<B, KB + 1>::run(W, m, n, p, q, lane, pi, hsub, L);
   }
@@ -281,13 +284,16 @@ __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const 
                                          const double* __restrict__ vp,
                                          Partial* __restrict__ out, Lds& L, const int acc_dd) {
   constexpr int LD = 8 * B;
-  const int lane = threadIdx.x & 63;
-  const int p = lane >> 3, q = lane & 7;
+  const int lane0 = threadIdx.x & 63;
   const int m = P.m, H = P.H, n = P.n;
-  TermIter it = term_begin(P, t0, lane);
+  TermIter it = term_begin(P, t0, lane0);
   dd acc = {0.0, 0.0};
   double sabs = 0.0;
   for (int64_t t = t0; t < t1; ++t) {
+    // lane index of this term (optionally opaque, see LH_OPAQUE_TERM)
+    int lane = lane0;
+    LH_OPAQUE(LH_OPAQUE_TERM, lane);
+    const int p = lane >> 3, q = lane & 7;
     if (t != t0) term_next(it, H, lane);
     double coef;
     bool empty;
@@ -317,7 +323,7 @@ __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const 
     sabs = fma(fabs(coef), fabs(f), sabs);
     wave_sync();
   }
-  if (lane == 0) {
+  if (lane0 == 0) {
     Partial pr;
     pr.hr = acc.hi;
     pr.lr = acc.lo;
@@ -422,14 +428,16 @@ __global__ void finalize_kernel(const Prob* __restrict__ probs, const Partial* _
     dd_add(s, pr.hr, pr.lr);
     sabs += pr.abs_sum;
   }
-  const double v = (s.hi + s.lo) * P.scale;
+  double v = (s.hi + s.lo) * P.scale;
+  const bool bad = !isfinite(v) || !isfinite(sabs);
+  if (bad) v = NAN;  // non-finite input or overflow
   *out = v;
   if (err) {
     const double eps = 1.1102230246251565e-16;
     double rel_term = 4.0 * (P.m + 1) * eps;
     if (!acc_dd) rel_term += (double)(P.t1 - P.t0) * eps;
     double e = sabs * P.scale * rel_term;
-    if (!isfinite(v) || !isfinite(e)) e = INFINITY;
+    if (bad || !isfinite(e)) e = INFINITY;
     *err = e;
   }
 }

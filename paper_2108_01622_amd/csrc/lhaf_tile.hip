@@ -1,6 +1,6 @@
 // One register tile of one persistent-kernel family, as its own translation
 // unit.  Built once per (LH_FAMILY, LH_TILE):
-//   LH_FAMILY 0 forward_kernel<LH_TILE> (+ occupancy query)
+//   LH_FAMILY 0 forward_kernel<LH_TILE, ET and FDS> (+ occupancy query)
 //   LH_FAMILY 1 backward_kernel<LH_TILE> (+ occupancy query)
 //   LH_FAMILY 2 multi_kernel<LH_TILE, 0 and 1>
 //   LH_FAMILY 3 real::real_kernel<LH_TILE>
@@ -34,21 +34,28 @@ namespace lh {
 #if LH_FAMILY == 0
 template <int B>
 hipError_t launch_forward(const PersistArgs& a, const cd* ws, Partial* parts, int acc_dd,
-                          cd* saved) {
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(forward_kernel<B>), dim3(a.grid), dim3(64), a.lds, a.stream,
-                     a.probs, a.items, a.n_items, a.counter, ws, parts, acc_dd, a.nmax, saved);
+                          cd* saved, int et) {
+  if (et)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(forward_kernel<B, true>), dim3(a.grid), dim3(64), a.lds,
+                       a.stream, a.probs, a.items, a.n_items, a.counter, ws, parts, acc_dd, a.nmax,
+                       saved);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(forward_kernel<B, false>), dim3(a.grid), dim3(64), a.lds,
+                       a.stream, a.probs, a.items, a.n_items, a.counter, ws, parts, acc_dd, a.nmax,
+                       saved);
   return hipGetLastError();
 }
 template <int B>
-int resident_forward(size_t lds) {
+int resident_forward(size_t lds, int et) {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &blocks, reinterpret_cast<const void*>(&forward_kernel<B>), 64, lds) != hipSuccess)
-    return 0;
+  const void* fn = et ? reinterpret_cast<const void*>(&forward_kernel<B, true>)
+                      : reinterpret_cast<const void*>(&forward_kernel<B, false>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, 64, lds) != hipSuccess) return 0;
   return blocks;
 }
-template hipError_t launch_forward<LH_TILE>(const PersistArgs&, const cd*, Partial*, int, cd*);
-template int resident_forward<LH_TILE>(size_t);
+template hipError_t launch_forward<LH_TILE>(const PersistArgs&, const cd*, Partial*, int, cd*,
+                                            int);
+template int resident_forward<LH_TILE>(size_t, int);
 #elif LH_FAMILY == 1
 template <int B>
 hipError_t launch_backward(const PersistArgs& a, const cd* ws, cd* gslots, cd* scratch,

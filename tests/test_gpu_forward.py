@@ -135,3 +135,42 @@ def test_batched_shared_base_uneven(T, api, orc):
     for k, ix in enumerate(idx):
         want = orc.lhaf_memo(B[np.ix_(ix, ix)], gam[ix], prec="f128")
         assert rel(got[k], want) < 1e-11, k
+
+
+@pytest.mark.parametrize("N", [14, 27, 40])
+def test_et_term_ranges_with_pair_deletion(T, api, orc, N):
+    """ET terms run on their kept pairs only (pairs with z_p = 0 deleted, so
+    a term's tile follows its popcount).  Single terms of every kept-pair
+    count and partial sums over ranges that mix counts follow the oracle's
+    ET enumeration at full m; N = 27 has a padding vertex."""
+    A, g = I.random_symmetric(N, 1400 + N, var=1.0 / N)
+    A = A.copy()
+    np.fill_diagonal(A, 0.0)
+    n = (N + 1) // 2
+    Tn = 2 ** n
+    ranges = [(1, 2), (2 ** (n - 1), 2 ** (n - 1) + 1), (Tn - 1, Tn), (3, 67), (Tn // 3, Tn // 3 + 200)]
+    for (t0, t1) in ranges:
+        want = orc.lhaf_sum(A, g, mode="et", t0=t0, t1=t1, scaled=False)
+        got = api.lhaf(dev(T, A), dev(T, g), sum="et", term_begin=t0, term_end=t1,
+                       scaled=False).item()
+        print(f"[case] ET N={N} terms [{t0},{t1})", flush=True)
+        assert rel(got, want) < 1e-11, (t0, t1, got, want)
+
+
+def test_et_mixed_tiles_one_launch(T, api, orc):
+    """One ET launch over problems of several tiles (N = 6 .. 24) on the
+    100-mode state: every value against the oracle's definition."""
+    base = I.state100(0)
+    B, gam = base["B"], base["gamma"]
+    rng = np.random.Generator(np.random.PCG64(2424))
+    sizes = [6, 24, 13, 18, 9, 22]
+    idx = [np.sort(rng.permutation(100)[:s]) for s in sizes]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    got = api.lhaf_batched(dev(T, B), dev(T, gam), idx=np.concatenate(idx), idx_off=off,
+                           sum="et").cpu().numpy()
+    for k, ix in enumerate(idx):
+        As, gs = B[np.ix_(ix, ix)], gam[ix]
+        want = orc.lhaf_memo(As, gs, prec="f128") if len(ix) <= 16 else \
+            orc.lhaf_sum(As, gs, mode="fds", prec="f64")
+        # ET cancels more than FDS (kappa_ET ~ 1e5 at N = 24): 1e-9
+        assert rel(got[k], want) < 1e-9, k

@@ -354,3 +354,48 @@ def test_lhafmix_sum_matches_definition(orc, n, mode):
     # the greedy pairing of the same pattern gives the same value
     other = orc.lhaf_repeated(A, g, np.concatenate([n, n]), method="sum", mode=mode, prec="f128")
     assert abs(other - want) <= 1e-12 * abs(want)
+
+
+# --------------------------------------------------------------------------
+# Sigma_t |c_t f_t| (the conditioning measure behind the kappa-scaled test
+# tolerances), pinned independently of the routine that accumulates it.
+def test_abs_sum_closed_form_n2(orc):
+    """At N = 2 the FDS sum has one (sign-halved) term and the ET sum one
+    non-empty term, each equal to the whole lhaf: Sigma |c_t f_t| must be
+    |A_12 + g_1 g_2| (scaled FDS) in both modes."""
+    A = np.array([[0.3, 0.7 - 0.2j], [0.7 - 0.2j, -1.1]])
+    g = np.array([0.4 + 0.1j, -0.9 + 0.5j])
+    want = abs(A[0, 1] + g[0] * g[1])
+    for mode in ("fds", "et"):
+        v, ab = orc.lhaf_sum(A, g, mode=mode, with_abs=True)
+        assert abs(ab - want) <= 1e-15 * want, mode
+
+
+@pytest.mark.parametrize("N,seed", [(6, 61), (9, 62), (12, 63)])
+@pytest.mark.parametrize("mode", ["fds", "et"])
+def test_abs_sum_matches_eigenvalue_route(orc, N, seed, mode):
+    """The C oracle's explicit-power sum and the numpy eigenvalue route
+    (independent code: eigenvalues of C X instead of matrix powers, the
+    exponential series by repeated convolution) give the same Sigma |c_t f_t|
+    over the full enumeration and over a partial range."""
+    A, g = I.random_symmetric(N, seed)
+    A = A.copy()
+    np.fill_diagonal(A, 0.0)
+    for (t0, t1) in ((0, -1), (3, 17)):
+        _, a1 = orc.lhaf_sum(A, g, mode=mode, t0=t0, t1=t1, with_abs=True)
+        _, a2 = orc.lhaf_eig_sum(A, g, mode=mode, t0=t0, t1=t1, with_abs=True)
+        assert abs(a1 - a2) <= 1e-11 * a2, (t0, t1, a1, a2)
+
+
+def test_abs_sum_is_termwise(orc):
+    """Sigma |c_t f_t| over a range is the sum of the moduli of the single-term
+    partial sums (not the modulus of a running sum) and bounds the value."""
+    A, g = I.random_symmetric(10, 64)
+    A = A.copy()
+    np.fill_diagonal(A, 0.0)
+    for mode in ("fds", "et"):
+        v, ab = orc.lhaf_sum(A, g, mode=mode, t0=2, t1=23, scaled=False, with_abs=True)
+        terms = [orc.lhaf_sum(A, g, mode=mode, t0=t, t1=t + 1, scaled=False) for t in range(2, 23)]
+        assert abs(ab - sum(abs(x) for x in terms)) <= 1e-13 * ab
+        assert abs(v) <= ab * (1 + 1e-14)
+        assert ab > 1.5 * abs(v)  # this range cancels: the check is not vacuous
