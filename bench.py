@@ -511,8 +511,7 @@ def main():
 
     def multi():
         out = {}
-        rng = np.random.Generator(np.random.PCG64(4040))
-        gs = g_np[0][None, :] + 0.05 * (rng.normal(size=(12, N)) + 1j * rng.normal(size=(12, N)))
+        _, gs = inputs.subdetector_gammas(12)
         gst = torch.as_tensor(gs, device=dev)
         A12 = A[:1].expand(12, N, N).contiguous()
         t_one = timed_once(lambda: api.lhaf_gammas(A[0], gst))
@@ -549,10 +548,7 @@ def main():
         out["mixed_state_m20"] = {"workload": f"lhafmix, 2M x 2M with M = 20, n = {nm.tolist()}, "
                                               f"N = {2 * int(nm.sum())}, FDS dd",
                                   "seconds": t_mix, "terms": Tm, "terms_per_s": Tm / t_mix}
-        rng = np.random.Generator(np.random.PCG64(4041))
-        Ar = rng.uniform(0.0, 0.2, size=(N, N))
-        Ar = 0.5 * (Ar + Ar.T)
-        gr = rng.uniform(0.0, 1.0, size=N)
+        Ar, gr = inputs.real_nonneg(N, 0)
         Art, grt = torch.as_tensor(Ar, device=dev), torch.as_tensor(gr, device=dev)
         t_real = timed_once(lambda: api.lhaf_real(Art, grt))
         t_cplx = timed_once(lambda: api.lhaf(Art.to(torch.complex128), grt.to(torch.complex128)))

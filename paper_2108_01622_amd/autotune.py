@@ -3,12 +3,15 @@
 The library cuts each problem's term space into items (term ranges) taken
 from an atomic queue by the resident wavefronts; a schedule fixes how many
 items are queued per resident wavefront (``lhaf_schedule_count()`` choices).
-Few large items cost less queue traffic and per-item setup; many small items
-balance uneven batches.  This tool times every schedule on synthetic
-Gaussian-state problems of each register tile (B = ceil(N/8)) and sum mode,
-and writes the fastest as lines ``B mode schedule`` to a cache file that the
-library reads through $LHAF_TUNE_CACHE (the binding points it at the shipped
-file when the variable is unset).
+Few large items cost less queue traffic and per-item setup (the backward
+also zeroes and reduces one gradient slot per item); many small items
+balance uneven batches and the tail of a launch.  This tool times every
+schedule on synthetic Gaussian-state problems of each register tile
+(B = ceil(N/8)) for three kinds of launch -- the ET forward, the FDS forward
+and the gradient pass (the fused value+adjoint kernel) -- and writes the
+fastest as lines ``B kind schedule`` (kind 0 ET, 1 FDS, 2 gradient pass) to
+a cache file that the library reads through $LHAF_TUNE_CACHE (the binding
+points it at the shipped file when the variable is unset).
 
     python -m paper_2108_01622_amd.autotune [--out FILE] [--sizes 16 24 ...]
 """
@@ -24,22 +27,23 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tune", "mi355x.txt")
+KINDS = {"et": 0, "fds": 1, "grad": 2}
 
 
-def _problems(N: int, rng):
+def _problems(N: int, rng, cap: int):
+    """A dense batch of Gaussian-state matrices of size N and the term range
+    that bounds one measurement to about `cap` terms in total."""
     from . import inputs
-    # enough terms to time, bounded: about 2^21 terms per measurement
-    cap = 1 << 21
     terms_each = 2 ** max(N // 2 - 1, 0)
     count = int(max(1, min(256, cap // max(terms_each, 1))))
     mats = [inputs.gaussian_state_matrix(N, rng) for _ in range(count)]
     A = np.stack([m[0] for m in mats])
     g = np.stack([m[1] for m in mats])
-    term_end = -1 if terms_each <= cap else cap
+    term_end = -1 if terms_each * count <= cap else max(1, cap // count)
     return A, g, term_end
 
 
-def tune(sizes=(16, 24, 32, 40, 48, 56, 64), modes=("fds", "et"), reps=2, verbose=True):
+def tune(sizes=(16, 24, 32, 40, 48, 56, 64), kinds=("et", "fds", "grad"), reps=2, verbose=True):
     import torch
     from . import api, _binding
     nsched = int(_binding.lib().lhaf_schedule_count())
@@ -47,13 +51,19 @@ def tune(sizes=(16, 24, 32, 40, 48, 56, 64), modes=("fds", "et"), reps=2, verbos
     best, report = {}, []
     for N in sizes:
         B = math.ceil(N / 8)
-        A_np, g_np, term_end = _problems(N, rng)
-        A = torch.as_tensor(A_np, device="cuda")
-        g = torch.as_tensor(g_np, device="cuda")
-        for mode in modes:
+        for kind in kinds:
+            # the gradient pass is ~4-30x slower per term: fewer terms
+            cap = (1 << 21) if kind != "grad" else (1 << 17 if N > 40 else 1 << 19)
+            A_np, g_np, term_end = _problems(N, rng, cap)
+            A = torch.as_tensor(A_np, device="cuda")
+            g = torch.as_tensor(g_np, device="cuda")
+            off = np.arange(len(A_np) + 1, dtype=np.int64) * N
+            grads = (torch.empty(api.lhaf_grads_count(off), dtype=torch.complex128, device="cuda")
+                     if kind == "grad" else None)
             times = []
             for s in range(nsched):
-                kw = dict(sum=mode, schedule=s, scaled=term_end < 0, term_end=term_end)
+                kw = dict(sum="et" if kind == "et" else "fds", schedule=s, scaled=term_end < 0,
+                          term_end=term_end, grads=grads)
                 api.lhaf_batched(A, g, **kw)
                 torch.cuda.synchronize()
                 t = time.perf_counter()
@@ -62,8 +72,8 @@ def tune(sizes=(16, 24, 32, 40, 48, 56, 64), modes=("fds", "et"), reps=2, verbos
                 torch.cuda.synchronize()
                 times.append((time.perf_counter() - t) / reps)
             k = int(np.argmin(times))
-            best[(B, mode)] = k
-            row = dict(N=N, B=B, mode=mode, batch=len(A_np), best=k,
+            best[(B, kind)] = k
+            row = dict(N=N, B=B, kind=kind, batch=len(A_np), term_end=term_end, best=k,
                        times_ms=[round(1e3 * x, 3) for x in times])
             report.append(row)
             if verbose:
@@ -74,9 +84,10 @@ def tune(sizes=(16, 24, 32, 40, 48, 56, 64), modes=("fds", "et"), reps=2, verbos
 def write_cache(best, path=DEFAULT_CACHE):
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as f:
-        f.write("# B mode schedule (mode 0 = ET, 1 = FDS), written by paper_2108_01622_amd.autotune\n")
-        for (B, mode), s in sorted(best.items()):
-            f.write(f"{B} {1 if mode == 'fds' else 0} {s}\n")
+        f.write("# tile kind schedule (kind 0 = ET forward, 1 = FDS forward, 2 = gradient pass), "
+                "written by paper_2108_01622_amd.autotune\n")
+        for (B, kind), s in sorted(best.items(), key=lambda x: (x[0][0], KINDS[x[0][1]])):
+            f.write(f"{B} {KINDS[kind]} {s}\n")
     return path
 
 
@@ -84,9 +95,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_CACHE)
     ap.add_argument("--sizes", type=int, nargs="*", default=[16, 24, 32, 40, 48, 56, 64])
-    ap.add_argument("--modes", nargs="*", default=["fds", "et"])
+    ap.add_argument("--kinds", nargs="*", default=["et", "fds", "grad"])
     a = ap.parse_args()
-    best, _ = tune(a.sizes, a.modes)
+    best, _ = tune(a.sizes, a.kinds)
     print("wrote", write_cache(best, a.out))
 
 

@@ -88,17 +88,19 @@ const Schedule kSchedules[] = {{1}, {2}, {4}, {8}, {16}, {32}};
 const int kNumSchedules = (int)(sizeof(kSchedules) / sizeof(kSchedules[0]));
 const int kDefaultSchedule = 2;
 
-// schedule cache: lines "bclass mode schedule" from $LHAF_TUNE_CACHE
+// schedule cache: lines "tile kind schedule" from $LHAF_TUNE_CACHE, kind 0 =
+// ET forward, 1 = FDS forward, 2 = gradient pass (fused or backward, either
+// sum)
 struct TuneCache {
   bool loaded = false;
-  int best[9][2];
+  int best[9][3];
 };
 TuneCache g_tune;
 
-int pick_schedule(const lh_opts* o, int bmax, int mode) {
+int pick_schedule(const lh_opts* o, int bmax, int kind) {
   if (o && o->schedule >= 0 && o->schedule < kNumSchedules) return o->schedule;
   if (!g_tune.loaded) {
-    for (auto& r : g_tune.best) r[0] = r[1] = -1;
+    for (auto& r : g_tune.best) r[0] = r[1] = r[2] = -1;
     const char* path = std::getenv("LHAF_TUNE_CACHE");
     if (path) {
       if (FILE* f = std::fopen(path, "r")) {
@@ -106,8 +108,8 @@ int pick_schedule(const lh_opts* o, int bmax, int mode) {
         while (std::fgets(line, sizeof(line), f)) {
           int b, md, s;
           if (line[0] == '#') continue;
-          if (std::sscanf(line, "%d %d %d", &b, &md, &s) == 3 && b >= 1 && b <= 8 &&
-              (md == 0 || md == 1) && s >= 0 && s < kNumSchedules)
+          if (std::sscanf(line, "%d %d %d", &b, &md, &s) == 3 && b >= 1 && b <= 8 && md >= 0 &&
+              md <= 2 && s >= 0 && s < kNumSchedules)
             g_tune.best[b][md] = s;
         }
         std::fclose(f);
@@ -115,7 +117,7 @@ int pick_schedule(const lh_opts* o, int bmax, int mode) {
     }
     g_tune.loaded = true;
   }
-  int s = g_tune.best[bmax][mode ? 1 : 0];
+  int s = g_tune.best[bmax][kind];
   return s >= 0 ? s : kDefaultSchedule;
 }
 
@@ -217,7 +219,7 @@ lh_status build_plan(std::vector<ProblemIn>& pin, const lh_opts& o, int dev, Pla
       total_cost += (double)(P.t1 - P.t0) * term_cost(P.B);
     }
   }
-  const int sched = pick_schedule(&o, pl.bmax, mode_any);
+  const int sched = pick_schedule(&o, pl.bmax, for_backward ? 2 : (mode_any ? 1 : 0));
   const Schedule S = kSchedules[sched];
   const int cus = g_dev[dev].cus;
   const int waves =

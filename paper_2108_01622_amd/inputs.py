@@ -218,3 +218,25 @@ def random_symmetric(n: int, seed: int, var: float = 1.0):
     a = 0.5 * (a + a.T)
     g = complex_normal(rng, n, var)
     return a.astype(np.complex128), g.astype(np.complex128)
+
+
+# --------------------------------------------------------------------------
+# sub-detector batching: loop-weight vectors around one grad40 matrix's
+def subdetector_gammas(count: int = 12):
+    """grad40 matrix 0 and `count` loop-weight vectors gamma_0 + 0.05 (x + i y),
+    x, y iid N(0, 1) (the loop vectors of neighbouring sub-detector outcomes)."""
+    A, g = grad40(count=1)
+    rng = rng_for(6, 0)
+    n = A.shape[1]
+    gs = g[0][None, :] + 0.05 * (rng.normal(size=(count, n)) + 1j * rng.normal(size=(count, n)))
+    return A[0], gs.astype(np.complex128)
+
+
+# real non-negative matrices (independence-proposal weights)
+def real_nonneg(n: int, instance: int = 0):
+    """Symmetric A with A_ij ~ U[0, 0.2] (i < j), gamma_i ~ U[0, 1], real."""
+    rng = rng_for(7, instance)
+    a = rng.uniform(0.0, 0.2, size=(n, n))
+    a = 0.5 * (a + a.T)
+    g = rng.uniform(0.0, 1.0, size=n)
+    return a, g

@@ -33,11 +33,18 @@ TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def kernel_source_hash() -> str:
-    """SHA-256 over the HIP sources and headers the kernels are built from."""
+    """SHA-256 over the sources the persistent kernels are compiled from (the
+    kernel files, device and internal headers, the per-tile unit and the
+    public header) and the shipped schedule table, which sets their launch
+    shape.  The host API unit (lhaf_api.hip: validation, planning, small
+    set-up kernels) and the planner are left out, so a host-side change does
+    not invalidate a traffic record of an unchanged kernel."""
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")) +
+    files = sorted([f for f in glob.glob(os.path.join(HERE, "csrc", "*.hip"))
+                    if os.path.basename(f) != "lhaf_api.hip"] +
                    glob.glob(os.path.join(HERE, "csrc", "*.h")) +
-                   glob.glob(os.path.join(ROOT, "include", "*.h")))
+                   glob.glob(os.path.join(ROOT, "include", "*.h")) +
+                   [os.path.join(HERE, "tune", "mi355x.txt")])
     for f in files:
         h.update(os.path.basename(f).encode())
         h.update(open(f, "rb").read())

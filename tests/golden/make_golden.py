@@ -34,6 +34,7 @@ GRAD40_SAMPLE = [0, 37, 101, 255]
 CHAIN_PER_SIZE = 2
 DENSE52_BLOCK = 10
 DENSE60_BLOCK = 4
+GAMMAS40_SAMPLE = [0, 5, 11]
 
 
 def cx(z):
@@ -101,6 +102,19 @@ def jobs():
                 return dict(method="block_f128", value=cx(v1 * v2), halves=[cx(v1), cx(v2)],
                             sha256=I.sha256_of(A, g))
             J[f"block{n}/{k}"] = bjob
+    A1, gs = I.subdetector_gammas()
+    for k in GAMMAS40_SAMPLE:
+        def gjob(k=k):
+            v, ab = O.lhaf_sum(A1, gs[k], mode="fds", prec="f64", with_abs=True)
+            return dict(method="fds_f64", value=cx(v), abs_sum=ab, sha256=I.sha256_of(A1, gs[k]))
+        J[f"gammas40/{k}"] = gjob
+    for n in (24, 40):
+        def rjob(n=n):
+            a, g = I.real_nonneg(n, 0)
+            v, ab = O.lhaf_sum(a.astype(complex), g.astype(complex), mode="fds", prec="f64",
+                               with_abs=True)
+            return dict(method="fds_f64", value=cx(v), abs_sum=ab, sha256=I.sha256_of(a, g))
+        J[f"real{n}/0"] = rjob
     return J
 
 

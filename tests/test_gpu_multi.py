@@ -136,3 +136,25 @@ def test_gammas_n40_matches_batched(T, api):
     # both are correct to their rounding: within the sum of the error estimates
     assert np.all(np.abs(got - want) <= e1.cpu().numpy() + e2.cpu().numpy())
     assert np.all(relv(got, want) < 1e-9)
+
+
+def test_gammas_n40_vs_stored_oracle(T, api):
+    """N = 40, 12 sub-detector vectors in one pass: outputs 0, 5 and 11
+    against the oracle's FDS sums stored in tests/golden (written by
+    make_golden.py from oracle/ only); bound max(1e-11, 4 kappa u)."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_values.json")))
+    A, gs = I.subdetector_gammas()
+    got = api.lhaf_gammas(dev(T, A), dev(T, gs)).cpu().numpy()
+    keys = [k for k in gold if k.startswith("gammas40/")]
+    if not keys:
+        pytest.skip("no stored oracle values for gammas40")
+    for k in keys:
+        g = int(k.split("/")[1])
+        ent = gold[k]
+        want = complex(*ent["value"])
+        kappa = ent["abs_sum"] / abs(want)
+        r = abs(got[g] - want) / abs(want)
+        print(f"[measure] {k} rel {r:.3e} kappa {kappa:.3e}", flush=True)
+        assert r < max(1e-11, 4 * kappa * 2.0 ** -53), (k, r)

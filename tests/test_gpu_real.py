@@ -71,3 +71,24 @@ def test_real_matches_complex_kernel(T, api, N):
                        T.as_tensor(g.astype(complex), device="cuda"), return_error=True)
     assert abs(got.item() - ref.item()) <= e1.item() + e2.item()
     assert rel(got.item(), ref.item()) < 1e-11
+
+
+@pytest.mark.parametrize("N", [24, 40])
+def test_real_vs_stored_oracle(T, api, N):
+    """Real non-negative N = 24 / 40 lhaf in the real kernel against the
+    oracle's FDS sum stored in tests/golden (oracle only); bound
+    max(1e-11, 4 kappa u)."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_values.json")))
+    key = f"real{N}/0"
+    if key not in gold:
+        pytest.skip(f"no stored oracle value for {key}")
+    A, g = I.real_nonneg(N, 0)
+    got = api.lhaf_real(T.as_tensor(A, device="cuda"), T.as_tensor(g, device="cuda")).item()
+    want = complex(*gold[key]["value"])
+    assert abs(want.imag) <= 1e-14 * abs(want.real)
+    kappa = gold[key]["abs_sum"] / abs(want)
+    r = abs(got - want.real) / abs(want)
+    print(f"[measure] {key} rel {r:.3e} kappa {kappa:.3e}", flush=True)
+    assert r < max(1e-11, 4 * kappa * 2.0 ** -53)

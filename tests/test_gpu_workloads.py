@@ -181,3 +181,17 @@ def test_block52_vs_float128(T, api, k):
     want = gold(f"block52/{k}")
     print("block52", k, got, want, rel(got, want), flush=True)
     assert rel(got, want) < 1e-9
+
+
+def test_block60_vs_float128(T, api):
+    """N = 60 (2^29 FDS terms, register tile 8): C = A1 (+) A2 against the
+    __float128 product of its halves (App. B.4's accuracy protocol; the paper
+    bounds its own FDS by 1e-8 at N = 60).  About three minutes."""
+    A, g, _, _ = I.block_diagonal_stress(60, 0)
+    print("[case] block60/0 full sum", flush=True)
+    got, err = api.lhaf(dev(T, A), dev(T, g), return_error=True)
+    want = gold("block60/0")
+    r = rel(got.item(), want)
+    print(f"[measure] block60/0 rel {r:.3e} err_est/|x| {err.item() / abs(want):.3e}", flush=True)
+    assert r < 1e-9
+    assert abs(got.item() - want) <= err.item()
