@@ -402,8 +402,14 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
 #pragma unroll
     for (int k = 0; k < B; ++k) G[(8 * a + (lane0 >> 3)) * LD + 8 * k + (lane0 & 7)] = czero();
 
+  // Paterson-Stockmeyer split s = ceil(sqrt n); for tiles whose powers live
+  // in the global scratch, lowered while the product count (s - 1) +
+  // ceil(n / s) - 1 stays the same, so fewer powers are stored and re-read
+  // (n = 26: s = 4 instead of 6, 3 stored powers instead of 5)
   int s = 1;
   while (s * s < n) ++s;
+  if constexpr (!kStage)
+    while (s > 2 && (s - 2) + (n + s - 2) / (s - 1) <= (s - 1) + (n + s - 1) / s) --s;
   const int Q = (n + s - 1) / s - 1;
   dd accr = {0.0, 0.0}, acci = {0.0, 0.0};
   double sabs = 0.0;

@@ -40,6 +40,13 @@ static __constant__ BinomTable c_binom = make_binom_table();
     if (flag) asm volatile("" : "+v"(v)); \
   } while (0)
 
+// Per-term relative rounding error of the Hessenberg / characteristic-
+// polynomial evaluation assumed by the error estimates, in units of u per
+// matrix dimension m + 1.  Typical terms stay within a few u; the largest
+// per-term error seen is about 6 (m + 1) u (mixed-state pairing (i, M + i),
+// m = 20, where the signed sum cancels by 5e6), so the estimate takes 8.
+constexpr double kTermErrPerDim = 8.0;
+
 struct cd {
   double r, i;
 };
@@ -69,6 +76,10 @@ __device__ __forceinline__ cd cfnma(cd a, cd b, cd c) {
 __device__ __forceinline__ cd cjfma(cd a, cd b, cd c) {
   return mk(fma(a.r, b.r, fma(a.i, b.i, c.r)), fma(a.r, b.i, fma(-a.i, b.r, c.i)));
 }
+// c - a*conj(b)
+__device__ __forceinline__ cd cfnmaj(cd a, cd b, cd c) {
+  return mk(fma(-a.r, b.r, fma(-a.i, b.i, c.r)), fma(-a.i, b.r, fma(a.r, b.i, c.i)));
+}
 // a*conj(b)
 __device__ __forceinline__ cd cmulj(cd a, cd b) {
   return mk(fma(a.r, b.r, a.i * b.i), fma(a.i, b.r, -a.r * b.i));
@@ -78,16 +89,29 @@ __device__ __forceinline__ double cabs2(cd a) { return fma(a.r, a.r, a.i * a.i);
 // ---------------------------------------------------------------------------
 // Lane grid: lane = 8*p + q.  "Row group" = the 8 lanes sharing p (consecutive
 // lanes), "column group" = the 8 lanes sharing q (stride 8).
+// Value of a permuted lane for the lane permutations used below (quad
+// permutes, row_ror, row_half_mirror), each of which reads a valid lane for
+// every lane: with bound_ctrl and full masks the old value of the destination
+// is never used, so the move needs no copy of its source.
+#ifndef LH_DPP_BOUND
+#define LH_DPP_BOUND 1
+#endif
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double x) {
   int lo = __double2loint(x), hi = __double2hiint(x);
-  lo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
-  hi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+  if constexpr (LH_DPP_BOUND) {
+    lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true);
+    hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true);
+  } else {
+    lo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+  }
   return __hiloint2double(hi, lo);
 }
 
-// x + (value of the lane 16 apart): permlane16_swap exchanges 16-lane rows
-// 0<->1 and 2<->3; both outputs together hold the pair.
+// x + (value of the lane 16 apart): permlane16_swap exchanges the odd 16-lane
+// rows of its first operand with the even rows of its second, so with x in
+// both the two outputs together hold every lane's value and its partner's.
 __device__ __forceinline__ double sum_xor16(double x) {
   int lo = __double2loint(x), hi = __double2hiint(x);
   auto L = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
@@ -99,6 +123,24 @@ __device__ __forceinline__ double sum_xor32(double x) {
   auto L = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
   auto H = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
   return __hiloint2double(H[0], L[0]) + __hiloint2double(H[1], L[1]);
+}
+// Two different values through one swap: rows 0 and 2 receive a + (a of the
+// lane 16 apart), rows 1 and 3 the same sum of b (no register copies).
+__device__ __forceinline__ double sum_xor16_pair(double a, double b) {
+  int alo = __double2loint(a), ahi = __double2hiint(a);
+  int blo = __double2loint(b), bhi = __double2hiint(b);
+  auto L = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+  auto H = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+  return __hiloint2double(H[0], L[0]) + __hiloint2double(H[1], L[1]);
+}
+// Inverse of the pairing: from x holding a in rows 0, 2 and b in rows 1, 3,
+// a and b on every lane.
+__device__ __forceinline__ void unpair_rows16(double x, double& a, double& b) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  auto L = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  auto H = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  a = __hiloint2double(H[0], L[0]);
+  b = __hiloint2double(H[1], L[1]);
 }
 
 // Sum over the row group (xor 1, xor 2 by quad permutes, then lane i with
@@ -126,7 +168,21 @@ __device__ __forceinline__ double sum_half32(double x) {
 }
 __device__ __forceinline__ cd sum_half32(cd a) { return mk(sum_half32(a.r), sum_half32(a.i)); }
 __device__ __forceinline__ cd sum_row8(cd a) { return mk(sum_row8(a.r), sum_row8(a.i)); }
-__device__ __forceinline__ cd sum_col8(cd a) { return mk(sum_col8(a.r), sum_col8(a.i)); }
+// Complex column-group sum: after the xor-8 step the real and imaginary parts
+// share one register through the paired xor-16 swap, take the xor-32 step
+// together and are separated again (every lane of a column group ends with
+// the same bits).
+#ifndef LH_COL_PAIR
+#define LH_COL_PAIR 1
+#endif
+__device__ __forceinline__ cd sum_col8(cd a) {
+  if constexpr (!LH_COL_PAIR) return mk(sum_col8(a.r), sum_col8(a.i));
+  double r = a.r + dpp_d<0x128>(a.r);  // row_ror:8
+  double i = a.i + dpp_d<0x128>(a.i);
+  double x = sum_xor32(sum_xor16_pair(r, i));
+  unpair_rows16(x, r, i);
+  return mk(r, i);
+}
 __device__ __forceinline__ cd sum_xor32(cd a) { return mk(sum_xor32(a.r), sum_xor32(a.i)); }
 
 // Value of lane 8p + r for every lane of row group p (r compile-time): DPP

@@ -61,6 +61,10 @@ __device__ __forceinline__ int ring_slot(int k, int NR) {
   return s >= NR ? s - NR : s;
 }
 
+#ifndef LH_FUSED_CONJ_UPDATE
+#define LH_FUSED_CONJ_UPDATE 1
+#endif
+
 // -------------------------------------------------------------------------
 // One Householder step of the Hessenberg reduction: column j (= 8*kb + jj)
 // is reduced below the subdiagonal by W <- P W P, P = I - tau w w^* (P is
@@ -165,7 +169,8 @@ __device__ __forceinline__ void householder_step(double (&Wr)[B][B], double (&Wi
 #pragma unroll
       for (int k = 0; k < B; ++k) {
         if (k < kb) continue;
-        const cd w_ = csub(mk(Wr[a][k], Wi[a][k]), cmulj(y, wc[k]));
+        const cd w_ = LH_FUSED_CONJ_UPDATE ? cfnmaj(y, wc[k], mk(Wr[a][k], Wi[a][k]))
+                                           : csub(mk(Wr[a][k], Wi[a][k]), cmulj(y, wc[k]));
         Wr[a][k] = w_.r;
         Wi[a][k] = w_.i;
       }
@@ -758,10 +763,12 @@ __global__ void finalize_kernel(const Prob* __restrict__ probs, int nprob,
   out[b] = o;
   if (err) {
     // per-term relative error of the Hessenberg / characteristic-polynomial
-    // evaluation ~ m * eps; plain FP64 accumulation adds ~ terms * eps.
+    // evaluation: kTermErrPerDim (m + 1) eps of every |c_t f_t|
     const double eps = 1.1102230246251565e-16;
-    double rel_term = 4.0 * (P.m + 1) * eps;
-    if (!acc_dd) rel_term += (double)(P.t1 - P.t0) * eps;
+    double rel_term = kTermErrPerDim * (P.m + 1) * eps;
+    // plain FP64 sums each item's terms in order in one wavefront and the
+    // item partials in double-double: the longest item bounds its rounding
+    if (!acc_dd) rel_term += (double)lh_longest_item(P) * eps;
     double e = sabs * rel_term;
     if (bad || !isfinite(e)) e = INFINITY;
     err[b] = e;

@@ -43,6 +43,13 @@ struct Item {
   int64_t t0, t1;
 };
 
+// Terms of the longest item of a problem: the planner cuts [t0, t1) into
+// n_items ranges of equal length up to one term.
+__host__ __device__ inline int64_t lh_longest_item(const Prob& P) {
+  const int64_t k = P.n_items > 0 ? P.n_items : 1;
+  return (P.t1 - P.t0 + k - 1) / k;
+}
+
 // Partial sum of one item: double-double complex + sum of |c_t f_t|.
 struct Partial {
   double hr, hi, lr, li, abs_sum, pad0, pad1, pad2;

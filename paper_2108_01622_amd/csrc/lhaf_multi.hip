@@ -246,8 +246,10 @@ __global__ void finalize_multi_kernel(const Prob* __restrict__ probs,
   out[o] = r;
   if (err) {
     const double eps = 1.1102230246251565e-16;
-    double rel_term = 4.0 * (P.m + 1) * eps;
-    if (!acc_dd) rel_term += (double)(P.t1 - P.t0) * eps;
+    double rel_term = kTermErrPerDim * (P.m + 1) * eps;
+    // plain FP64 sums each item's terms in order in one wavefront and the
+    // item partials in double-double: the longest item bounds its rounding
+    if (!acc_dd) rel_term += (double)lh_longest_item(P) * eps;
     double e = sabs * sc * rel_term;
     if (bad || !isfinite(e)) e = INFINITY;
     err[o] = e;

@@ -434,8 +434,10 @@ __global__ void finalize_kernel(const Prob* __restrict__ probs, const Partial* _
   *out = v;
   if (err) {
     const double eps = 1.1102230246251565e-16;
-    double rel_term = 4.0 * (P.m + 1) * eps;
-    if (!acc_dd) rel_term += (double)(P.t1 - P.t0) * eps;
+    double rel_term = kTermErrPerDim * (P.m + 1) * eps;
+    // plain FP64 sums each item's terms in order in one wavefront and the
+    // item partials in double-double: the longest item bounds its rounding
+    if (!acc_dd) rel_term += (double)lh_longest_item(P) * eps;
     double e = sabs * P.scale * rel_term;
     if (bad || !isfinite(e)) e = INFINITY;
     *err = e;

@@ -13,6 +13,23 @@
 #error "LH_FAMILY (0 forward, 1 backward, 2 multi, 3 real) must be defined"
 #endif
 
+// Code-generation choices of the wavefront reductions and the Hessenberg
+// update, per tile (measured on MI355X, M terms/s, defaults vs the
+// alternative): copy-free DPP moves and the paired complex column sum win up
+// to tile 7 (forward N = 40: 15.4 vs 14.5 / 15.1, N = 52: 5.26 vs 4.97 /
+// 5.14); at tile 8 the register file is full and the forward is fastest with
+// neither and the two-step conjugate update (3.03 vs 2.24); the tile-7
+// gradient pass is fastest with the in-place DPP moves (0.89 vs 0.69).
+#ifndef LH_DPP_BOUND
+#define LH_DPP_BOUND (LH_TILE <= 6 || (LH_TILE == 7 && LH_FAMILY != 1))
+#endif
+#ifndef LH_COL_PAIR
+#define LH_COL_PAIR (LH_TILE <= 7)
+#endif
+#ifndef LH_FUSED_CONJ_UPDATE
+#define LH_FUSED_CONJ_UPDATE (LH_TILE <= 7)
+#endif
+
 #include "lhaf.h"
 #include "lhaf_device.h"
 #include "lhaf_internal.h"
