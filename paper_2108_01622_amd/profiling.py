@@ -9,6 +9,9 @@ run -- python bench.py`).
         --fetch DIR/f_counter_collection.csv --write DIR/w_counter_collection.csv \\
         --kernel "backward_kernel<5>" --terms T --copy-bytes 1073741824 \\
         --command "..." --title "..."                      > profiles/NAME.md
+    python -m paper_2108_01622_amd.profiling issue DIR/a_counter_collection.csv \\
+        DIR/b_counter_collection.csv --kernel "forward_kernel<5, false>" --terms T \\
+        --command "..." --title "..."                      > profiles/NAME.md
 
 `traffic` turns the FETCH_SIZE and WRITE_SIZE counters (KiB per dispatch)
 into HBM bytes: each counter is scaled by the factor that makes it read the
@@ -130,6 +133,43 @@ def traffic_md(fetch_csv: str, write_csv: str, kernel: str, terms: int, copy_byt
     return "\n".join(out) + "\n"
 
 
+ISSUE_COUNTERS = ["SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU",
+                  "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_WAIT_INST_ANY", "SQ_INSTS_VALU_FMA_F64",
+                  "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64"]
+
+
+def issue_md(csvs, kernel: str, terms: int, command: str, title: str) -> str:
+    """Instruction-issue summary of the last dispatch of `kernel` from SQ
+    counter files (one or more rocprofv3 --pmc passes): instructions per term
+    by class and the fraction of each wavefront's cycles spent issuing VALU
+    instructions."""
+    val = {}
+    for path in csvs:
+        last = {}
+        for r in csv.DictReader(open(path)):
+            if _short(r["Kernel_Name"]) != kernel:
+                continue
+            d = int(r["Dispatch_Id"])
+            last.setdefault(r["Counter_Name"], {})[d] = float(r["Counter_Value"])
+        for c, by in last.items():
+            val[c] = by[max(by)]
+    if not val:
+        raise SystemExit(f"kernel {kernel} not found in the counter files")
+    out = [f"# {title}", "", "Commands (one rocprofv3 --pmc pass per counter set, from /tmp, "
+           "TMPDIR=/tmp):", f"`{command}`", "", f"Terms in the dispatch: {terms}.", "",
+           "| Counter | Value | Per term |", "|:--|--:|--:|"]
+    for c in ISSUE_COUNTERS:
+        if c in val:
+            out.append(f"| {c} | {val[c]:.4g} | {val[c] / terms:.4g} |")
+    if "SQ_ACTIVE_INST_VALU" in val and "SQ_WAVE_CYCLES" in val:
+        out += ["", "VALU issue per wavefront cycle (SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES): "
+                f"{val['SQ_ACTIVE_INST_VALU'] / val['SQ_WAVE_CYCLES']:.3f}"]
+    if "SQ_INSTS_VALU_FMA_F64" in val and "SQ_INSTS_VALU" in val:
+        out.append("FP64 FMA share of the VALU instructions: "
+                   f"{val['SQ_INSTS_VALU_FMA_F64'] / val['SQ_INSTS_VALU']:.3f}")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -146,9 +186,17 @@ def main(argv=None):
     t.add_argument("--command", required=True)
     t.add_argument("--title", default="rocprofv3 memory traffic")
     t.add_argument("--no-json", action="store_true")
+    i = sub.add_parser("issue")
+    i.add_argument("csv", nargs="+")
+    i.add_argument("--kernel", required=True)
+    i.add_argument("--terms", type=int, required=True)
+    i.add_argument("--command", required=True)
+    i.add_argument("--title", default="rocprofv3 instruction issue")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         sys.stdout.write(stats_md(a.csv, a.command, a.title))
+    elif a.cmd == "issue":
+        sys.stdout.write(issue_md(a.csv, a.kernel, a.terms, a.command, a.title))
     else:
         sys.stdout.write(traffic_md(a.fetch, a.write, a.kernel, a.terms, a.copy_bytes, a.command,
                                     a.title, not a.no_json))

@@ -60,3 +60,29 @@ def test_paterson_stockmeyer_products():
     # s = ceil(sqrt n) powers W^2..W^s, then ceil(n/s) - 1 Horner steps
     assert [bench.ps_products(n) for n in (1, 2, 4, 5, 9, 20, 26, 32)] == [0, 1, 2, 3, 4, 7, 9, 10]
     assert bench.canonical_flops(40, 20) == pytest.approx(40 / 3 * 40 ** 3 + 8 * 20 * 1600)
+
+
+def test_issue_summary_takes_last_dispatch_of_each_pass(prof, tmp_path):
+    """Counters of the kernel's last dispatch, from two passes, per term."""
+    kname = "void lh::forward_kernel<5, false>(lh::Prob const*, int)"
+    a = tmp_path / "a.csv"
+    b = tmp_path / "b.csv"
+    with open(a, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
+        w.writerow([1, kname, 64, "SQ_INSTS_VALU", 999.0])        # earlier dispatch: ignored
+        w.writerow([3, kname, 64, "SQ_INSTS_VALU", 4000.0])
+        w.writerow([3, kname, 64, "SQ_ACTIVE_INST_VALU", 4000.0])
+        w.writerow([3, kname, 64, "SQ_WAVE_CYCLES", 10000.0])
+        w.writerow([2, "void lh::pack_kernel(int)", 64, "SQ_INSTS_VALU", 5.0])
+    with open(b, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
+        w.writerow([3, kname, 64, "SQ_INSTS_VALU_FMA_F64", 1000.0])
+    md = prof.issue_md([str(a), str(b)], "forward_kernel<5, false>", 100, "cmd", "t")
+    assert "| SQ_INSTS_VALU | 4000 | 40 |" in md
+    assert "| SQ_INSTS_VALU_FMA_F64 | 1000 | 10 |" in md
+    assert "SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES): 0.400" in md
+    assert "FP64 FMA share of the VALU instructions: 0.250" in md
+    with pytest.raises(SystemExit):
+        prof.issue_md([str(a)], "backward_kernel<5>", 100, "cmd", "t")
