@@ -167,6 +167,13 @@ def issue_md(csvs, kernel: str, terms: int, command: str, title: str) -> str:
     if "SQ_INSTS_VALU_FMA_F64" in val and "SQ_INSTS_VALU" in val:
         out.append("FP64 FMA share of the VALU instructions: "
                    f"{val['SQ_INSTS_VALU_FMA_F64'] / val['SQ_INSTS_VALU']:.3f}")
+    if all(c in val for c in ("SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64",
+                              "SQ_INSTS_VALU_MUL_F64")):
+        # every wavefront instruction issues 64 lanes (masked lanes included)
+        flops = 64.0 * (2.0 * val["SQ_INSTS_VALU_FMA_F64"] + val["SQ_INSTS_VALU_ADD_F64"]
+                        + val["SQ_INSTS_VALU_MUL_F64"])
+        out.append(f"Executed FP64 flops per term (64 lanes x (2 FMA + ADD + MUL)): "
+                   f"{flops / terms:.4g}")
     return "\n".join(out) + "\n"
 
 

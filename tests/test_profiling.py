@@ -84,5 +84,20 @@ def test_issue_summary_takes_last_dispatch_of_each_pass(prof, tmp_path):
     assert "| SQ_INSTS_VALU_FMA_F64 | 1000 | 10 |" in md
     assert "SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES): 0.400" in md
     assert "FP64 FMA share of the VALU instructions: 0.250" in md
+    assert "Executed FP64 flops" not in md  # needs the ADD and MUL counts too
     with pytest.raises(SystemExit):
         prof.issue_md([str(a)], "backward_kernel<5>", 100, "cmd", "t")
+
+
+def test_issue_summary_executed_flops(prof, tmp_path):
+    kname = "void lh::forward_kernel<5, false>(lh::Prob const*, int)"
+    a = tmp_path / "a.csv"
+    with open(a, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
+        for c, v in (("SQ_INSTS_VALU_FMA_F64", 10.0), ("SQ_INSTS_VALU_ADD_F64", 3.0),
+                     ("SQ_INSTS_VALU_MUL_F64", 2.0)):
+            w.writerow([1, kname, 64, c, v])
+    md = prof.issue_md([str(a)], "forward_kernel<5, false>", 4, "cmd", "t")
+    # 64 lanes x (2 x 10 + 3 + 2) = 1600 flops over 4 terms
+    assert "Executed FP64 flops per term (64 lanes x (2 FMA + ADD + MUL)): 400" in md
