@@ -41,6 +41,7 @@ def measure(N: int, instances, modes, log=sys.stderr):
         gt = torch.as_tensor(g, device="cuda")
         for mode in modes:
             sm, am = mode.split("/")
+            print(f"[precision] {key} {mode} ...", file=log, flush=True)
             torch.cuda.synchronize()
             t = time.perf_counter()
             v, e = api.lhaf(At, gt, sum=sm, acc=am, return_error=True)
@@ -73,12 +74,13 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--n52", type=int, default=10, help="block52 instances (stored: 10)")
     ap.add_argument("--n60", type=int, default=1, help="block60 instances (stored: 4)")
+    ap.add_argument("--from60", type=int, default=0, help="first block60 instance")
     ap.add_argument("--modes", nargs="*", default=["fds/dd", "fds/fp64", "et/dd", "et/fp64"])
     ap.add_argument("--modes60", nargs="*", default=["fds/dd", "fds/fp64"])
     a = ap.parse_args(argv)
     rows = measure(52, range(a.n52), a.modes)
     if a.n60 > 0:
-        rows += measure(60, range(a.n60), a.modes60)
+        rows += measure(60, range(a.from60, a.from60 + a.n60), a.modes60)
     sys.stdout.write(table(rows))
 
 
