@@ -189,6 +189,16 @@ __device__ __forceinline__ void mul_right_dpp(double (&Rr)[B][B], double (&Ri)[B
 #define LH_BWD_OPAQUE(unstaged) (unstaged)
 #endif
 __host__ __device__ constexpr int mul_group(int B) { return LH_MULG(B); }
+// Products of the unstaged tiles 6 and 7 in the LDS-staged form (all row
+// groups at once, DPP row broadcasts of R at compile-time rows, the next
+// operand row prefetched) with the operand read from the global scratch
+// instead of LDS: measured +9 % at B = 6 and +14 % at B = 7 over the
+// ds_bpermute rows (fused pass N = 48 1.74 vs 1.59, N = 52 1.01 vs 0.89 M
+// terms/s).  Tile 8 keeps one row group at a time (two full accumulators do
+// not fit the register file).
+#ifndef LH_UNSTAGED_DPP
+#define LH_UNSTAGED_DPP(B) ((B) == 6 || (B) == 7)
+#endif
 
 template <int B>
 __device__ __forceinline__ void mul_right(double (&Rr)[B][B], double (&Ri)[B][B],
@@ -533,6 +543,7 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
     const int nsteps = (s - 1) + Q;
     for (int step = 0; step < nsteps; ++step) {
       if constexpr (kStage) mul_right_dpp<B>(Rr, Ri, X, q);
+      else if constexpr (LH_UNSTAGED_DPP(B)) mul_right_dpp<B>(Rr, Ri, step < s - 1 ? Wop : Yop, q);
       else mul_right<B>(Rr, Ri, step < s - 1 ? Wop : Yop, p, q);
       if (step < s - 2) {
         store_mat<B>(Rr, Ri, pw + (step + 1) * LD * LD, p, q);  // W^{step+2}
