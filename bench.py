@@ -249,8 +249,12 @@ def main():
     fwd_s = float(np.mean(fwd_ms)) / 1e3
     F = canonical_flops(m, n)
     fwd_tf = F * terms / fwd_s / 1e12
-    fwd_kernel = f"forward_kernel<{math.ceil(N / 8)}>"
-    bwd_kernel = f"backward_kernel<{math.ceil(N / 8)}>"
+    tile = math.ceil(N / 8)
+    fwd_kernel = f"forward_kernel<{tile}, {'true' if args.sum == 'et' else 'false'}>"
+    # the backward instance the library selects: LDS-staged up to tile 5 when
+    # it reads the coefficient store, up to tile 4 when it recomputes them
+    staged = tile <= (5 if args.mode == "store" else 4)
+    bwd_kernel = f"backward_kernel<{tile}, {'true' if staged else 'false'}>"
     fused = args.mode == "fused" and args.passes == "fwdbwd"
     if fused:
         # one launch (backward_kernel) evaluates every term's value and adjoint;

@@ -30,6 +30,7 @@ ARCH = os.environ.get("LHAF_OFFLOAD_ARCH", "gfx950")
 
 FAMILIES = {0: "lhaf_forward.hip", 1: "lhaf_backward.hip", 2: "lhaf_multi.hip", 3: "lhaf_real.hip"}
 TILES = range(1, 9)
+BWD_SPLIT_TILES = (5,)  # backward tiles with a staged and an unstaged instance
 _COMMON = ["lhaf.h", "lhaf_device.h", "lhaf_internal.h", "lhaf_forward.hip", "lhaf_launch.h"]
 
 
@@ -58,10 +59,15 @@ def _units(extra=()):
     for fam, ffile in FAMILIES.items():
         deps = _COMMON + ["lhaf_tile.hip"] + ([ffile] if fam else [])
         for b in sorted(TILES, reverse=True):  # largest tiles compile longest: start them first
-            obj = os.path.join(OBJDIR, f"tile_f{fam}_b{b}.o")
-            cmd = [cc, *_flags(extra), f"-DLH_FAMILY={fam}", f"-DLH_TILE={b}", "-c",
-                   _src("lhaf_tile.hip"), "-o", obj]
-            units.append((obj, cmd, deps))
+            # the backward tile with both an LDS-staged and an unstaged instance
+            # compiles them in separate units, so that the two occupancy targets
+            # do not meet in shared device functions
+            parts = [("", 0)] if not (fam == 1 and b in BWD_SPLIT_TILES) else [("", 1), ("u", 2)]
+            for suffix, unit in parts:
+                obj = os.path.join(OBJDIR, f"tile_f{fam}_b{b}{suffix}.o")
+                cmd = [cc, *_flags(extra), f"-DLH_FAMILY={fam}", f"-DLH_TILE={b}",
+                       f"-DLH_BWD_UNIT={unit}", "-c", _src("lhaf_tile.hip"), "-o", obj]
+                units.append((obj, cmd, deps))
     api_deps = sorted(set(_COMMON + list(FAMILIES.values()) + ["lhaf_api.hip"]))
     units.append((os.path.join(OBJDIR, "api.o"),
                   [cc, *_flags(extra), "-c", _src("lhaf_api.hip"), "-o", os.path.join(OBJDIR, "api.o")],

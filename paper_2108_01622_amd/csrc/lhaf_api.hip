@@ -169,13 +169,14 @@ struct Plan {
 };
 
 // wavefronts of one kernel instance resident per CU (occupancy query)
-int resident_per_cu(bool bwd, int bmax, int nmax, int et) {
-  const size_t lds = bwd ? bwd_lds_bytes(bmax, std::max(nmax, 1)) : lds_bytes_for(std::max(nmax, 1));
+int resident_per_cu(bool bwd, int bmax, int nmax, int et, bool staged) {
+  const size_t lds =
+      bwd ? bwd_lds_bytes(bmax, std::max(nmax, 1), staged) : lds_bytes_for(std::max(nmax, 1));
   int blocks = 0;
   switch (bmax) {
 #define LH_FN(BB)                                                      \
   case BB:                                                             \
-    blocks = bwd ? resident_backward<BB>(lds) : resident_forward<BB>(lds, et); \
+    blocks = bwd ? resident_backward<BB>(lds, staged) : resident_forward<BB>(lds, et); \
     break;
     LH_FN(1) LH_FN(2) LH_FN(3) LH_FN(4) LH_FN(5) LH_FN(6) LH_FN(7)
     default: LH_FN(8)
@@ -223,7 +224,8 @@ lh_status build_plan(std::vector<ProblemIn>& pin, const lh_opts& o, int dev, Pla
   const Schedule S = kSchedules[sched];
   const int cus = g_dev[dev].cus;
   const int waves =
-      std::max(1, cus * resident_per_cu(for_backward, pl.bmax, pl.nmax, o.sum == LH_SUM_ET));
+      std::max(1, cus * resident_per_cu(for_backward, pl.bmax, pl.nmax, o.sum == LH_SUM_ET,
+                                        bwd_staged(pl.bmax, o.saved != nullptr)));
   const double target = std::max(total_cost / ((double)waves * S.items_per_wave), 1e-9);
   struct Tmp {
     int prob;
@@ -900,14 +902,15 @@ static lh_status backward_impl(int32_t B, const lh_c128* A_base, int64_t lda, in
     cd* scratch = reinterpret_cast<cd*>(base + off_s);
     Partial* parts = fused ? reinterpret_cast<Partial*>(base + pl.lay.parts) : nullptr;
     if (!pl.items.empty()) {
-      const size_t lds = bwd_lds_bytes(pl.bmax, std::max(pl.nmax, 1));
+      const bool staged = bwd_staged(pl.bmax, o.saved != nullptr);
+      const size_t lds = bwd_lds_bytes(pl.bmax, std::max(pl.nmax, 1), staged);
       const PersistArgs pa = persist_args(pl, base, lds, st);
       const cd* wsc = reinterpret_cast<const cd*>(base + pl.lay.cdata);
       const cd* sv = reinterpret_cast<const cd*>(o.saved);
       hipError_t e;
       switch (pl.bmax) {
 #define LH_BCASE(BB) \
-  case BB: e = launch_backward<BB>(pa, wsc, gsl, scratch, sv, parts, acc_dd); break;
+  case BB: e = launch_backward<BB>(pa, wsc, gsl, scratch, sv, parts, acc_dd, staged); break;
         LH_BCASE(1) LH_BCASE(2) LH_BCASE(3) LH_BCASE(4) LH_BCASE(5) LH_BCASE(6) LH_BCASE(7)
         default: LH_BCASE(8)
 #undef LH_BCASE

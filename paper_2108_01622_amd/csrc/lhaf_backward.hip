@@ -24,7 +24,10 @@
 namespace lh {
 
 constexpr int kMaxPS = 6;      // ceil(sqrt(32))
-constexpr int kStageMaxB = 5;  // largest register tile with LDS staging
+#ifndef LH_STAGE_MAX_B
+#define LH_STAGE_MAX_B 5
+#endif
+constexpr int kStageMaxB = LH_STAGE_MAX_B;  // largest register tile with LDS staging
 
 // The same address as p, opaque to the optimiser (forces a fresh load).
 template <class T>
@@ -42,16 +45,30 @@ __host__ __device__ inline size_t bwd_item_elems(int B) {
   const size_t LD = 8 * (size_t)B;
   return LD * LD + 64;
 }
+// Which instance runs a backward launch of largest tile bmax: the LDS-staged
+// one (one wavefront per SIMD, the operand and Krylov vectors in LDS) for
+// tiles up to kStageMaxB when the coefficients come from the store, but only
+// up to LH_STAGE_RECOMPUTE_MAX_B when the launch recomputes them (fused pass
+// or recomputing backward): there tile 5 runs unstaged at two wavefronts per
+// SIMD, whose second wavefront hides the latency of the term's spectral
+// phase (measured at N = 40: fused pass 4.47 vs 4.19 M terms/s; from the
+// store the staged instance stays ahead, 6.82 vs 5.51).
+#ifndef LH_STAGE_RECOMPUTE_MAX_B
+#define LH_STAGE_RECOMPUTE_MAX_B 4
+#endif
+__host__ __device__ constexpr bool bwd_staged(int bmax, bool from_store) {
+  return bmax <= (from_store ? kStageMaxB : LH_STAGE_RECOMPUTE_MAX_B);
+}
 // complex elements of the LDS region X of a backward kernel instance (0
 // without staging): the larger of one LD x LD matrix and nmax Krylov vectors
 // of LD entries.
-__host__ __device__ inline size_t bwd_x_elems(int bmax, int nmax) {
-  if (bmax > kStageMaxB) return 0;
+__host__ __device__ inline size_t bwd_x_elems(int bmax, int nmax, bool staged) {
+  if (!staged) return 0;
   const size_t LD = 8 * (size_t)bmax;
   return LD * (LD > (size_t)nmax ? LD : (size_t)nmax);
 }
-inline size_t bwd_lds_bytes(int bmax, int nmax) {
-  return lds_bytes_for(nmax) + sizeof(cd) * bwd_x_elems(bmax, nmax);
+inline size_t bwd_lds_bytes(int bmax, int nmax, bool staged) {
+  return lds_bytes_for(nmax) + sizeof(cd) * bwd_x_elems(bmax, nmax, staged);
 }
 // Lanes of the wavefront exchange data through LDS only when staging (and
 // through the global scratch otherwise, which needs the full barrier).
@@ -197,7 +214,7 @@ __host__ __device__ constexpr int mul_group(int B) { return LH_MULG(B); }
 // terms/s).  Tile 8 keeps one row group at a time (two full accumulators do
 // not fit the register file).
 #ifndef LH_UNSTAGED_DPP
-#define LH_UNSTAGED_DPP(B) ((B) == 6 || (B) == 7)
+#define LH_UNSTAGED_DPP(B) ((B) >= 5 && (B) <= 7)
 #endif
 
 template <int B>
@@ -579,15 +596,18 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
   }
 }
 
-template <int BMAX>
 #ifndef LH_BWD_WAVES
-#define LH_BWD_WAVES(bmax) ((bmax) <= 1 ? 4 : ((bmax) <= 3 ? 2 : 1))
+#define LH_BWD_WAVES(bmax, stg) \
+  ((bmax) <= 1 ? 4 : ((bmax) <= 3 ? 2 : ((bmax) == 5 && !(stg) ? 2 : 1)))
 #endif
 #ifndef LH_BWD_ATTR
 #define LH_BWD_ATTR                   \
   __launch_bounds__(64) __attribute__( \
-      (amdgpu_waves_per_eu(LH_BWD_WAVES(BMAX), LH_BWD_WAVES(BMAX))))
+      (amdgpu_waves_per_eu(LH_BWD_WAVES(BMAX, kStg), LH_BWD_WAVES(BMAX, kStg))))
 #endif
+// kStg: operand and Krylov vectors in LDS (tiles <= kStageMaxB, see
+// bwd_staged), otherwise in the per-wavefront global scratch
+template <int BMAX, bool kStg>
 __global__ LH_BWD_ATTR void backward_kernel(const Prob* __restrict__ probs,
                                                       const Item* __restrict__ items, int n_items,
                                                       int* counter, const cd* __restrict__ ws,
@@ -612,7 +632,7 @@ __global__ LH_BWD_ATTR void backward_kernel(const Prob* __restrict__ probs,
 #define LH_BCASE(BB)                                                                   \
   case BB:                                                                             \
     if (BB <= BMAX)                                                                    \
-      run_item_bwd<(BB <= BMAX ? BB : 1), (BMAX <= kStageMaxB)>(                         \
+      run_item_bwd<(BB <= BMAX ? BB : 1), kStg>(                                         \
           P, I.t0, I.t1, Cp, vp, G, scr, L, saved, parts ? parts + I.pad : nullptr, acc_dd); \
     break;
       LH_BCASE(1)

@@ -32,9 +32,9 @@ hipError_t launch_forward(const PersistArgs& a, const cd* ws, Partial* parts, in
                           cd* saved, int et);
 // backward_kernel<B>: item gradient slots; per-wavefront scratch; with
 // `parts` (fused pass) also the item partials of the value
-template <int B>
-hipError_t launch_backward(const PersistArgs& a, const cd* ws, cd* gslots, cd* scratch,
-                           const cd* saved, Partial* parts, int acc_dd);
+template <int B, bool kStg>
+hipError_t launch_backward_as(const PersistArgs& a, const cd* ws, cd* gslots, cd* scratch,
+                              const cd* saved, Partial* parts, int acc_dd);
 // multi_kernel<B, MODE>: MODE 0 chain-rule outputs, 1 loop-weight vectors
 template <int B, int MODE>
 hipError_t launch_multi(const PersistArgs& a, const cd* ws, Partial* parts, int acc_dd,
@@ -47,7 +47,31 @@ hipError_t launch_real(const PersistArgs& a, const double* ws, Partial* parts, i
 // (occupancy query of the runtime; 0 if the query fails).
 template <int B>
 int resident_forward(size_t lds, int et);
+template <int B, bool kStg>
+int resident_backward_as(size_t lds);
+#if defined(LH_STAGE_MAX_B) && defined(LH_STAGE_RECOMPUTE_MAX_B)
+// the instance bwd_staged selected (only existing instances are referenced)
 template <int B>
-int resident_backward(size_t lds);
+inline hipError_t launch_backward(const PersistArgs& a, const cd* ws, cd* gslots, cd* scratch,
+                                  const cd* saved, Partial* parts, int acc_dd, int staged) {
+  if constexpr (B <= LH_STAGE_MAX_B) {
+    if (staged) return launch_backward_as<B, true>(a, ws, gslots, scratch, saved, parts, acc_dd);
+  }
+  if constexpr (B > LH_STAGE_RECOMPUTE_MAX_B) {
+    if (!staged) return launch_backward_as<B, false>(a, ws, gslots, scratch, saved, parts, acc_dd);
+  }
+  return hipErrorInvalidValue;
+}
+template <int B>
+inline int resident_backward(size_t lds, int staged) {
+  if constexpr (B <= LH_STAGE_MAX_B) {
+    if (staged) return resident_backward_as<B, true>(lds);
+  }
+  if constexpr (B > LH_STAGE_RECOMPUTE_MAX_B) {
+    if (!staged) return resident_backward_as<B, false>(lds);
+  }
+  return 0;
+}
+#endif
 
 }  // namespace lh

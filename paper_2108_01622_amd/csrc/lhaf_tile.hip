@@ -74,25 +74,38 @@ template hipError_t launch_forward<LH_TILE>(const PersistArgs&, const cd*, Parti
                                             int);
 template int resident_forward<LH_TILE>(size_t, int);
 #elif LH_FAMILY == 1
-template <int B>
-hipError_t launch_backward(const PersistArgs& a, const cd* ws, cd* gslots, cd* scratch,
-                           const cd* saved, Partial* parts, int acc_dd) {
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(backward_kernel<B>), dim3(a.grid), dim3(64), a.lds,
+// LH_BWD_UNIT: 0 every instance of the tile, 1 the LDS-staged one only, 2 the
+// unstaged one only (bwd_staged selects between them at launch)
+#ifndef LH_BWD_UNIT
+#define LH_BWD_UNIT 0
+#endif
+template <int B, bool kStg>
+hipError_t launch_backward_as(const PersistArgs& a, const cd* ws, cd* gslots, cd* scratch,
+                              const cd* saved, Partial* parts, int acc_dd) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(backward_kernel<B, kStg>), dim3(a.grid), dim3(64), a.lds,
                      a.stream, a.probs, a.items, a.n_items, a.counter, ws, gslots, scratch, a.nmax,
                      saved, parts, acc_dd);
   return hipGetLastError();
 }
-template <int B>
-int resident_backward(size_t lds) {
+template <int B, bool kStg>
+int resident_backward_as(size_t lds) {
   int blocks = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &blocks, reinterpret_cast<const void*>(&backward_kernel<B>), 64, lds) != hipSuccess)
+          &blocks, reinterpret_cast<const void*>(&backward_kernel<B, kStg>), 64, lds) !=
+      hipSuccess)
     return 0;
   return blocks;
 }
-template hipError_t launch_backward<LH_TILE>(const PersistArgs&, const cd*, cd*, cd*, const cd*,
-                                              Partial*, int);
-template int resident_backward<LH_TILE>(size_t);
+#if LH_BWD_UNIT != 2 && LH_TILE <= LH_STAGE_MAX_B
+template hipError_t launch_backward_as<LH_TILE, true>(const PersistArgs&, const cd*, cd*, cd*,
+                                                      const cd*, Partial*, int);
+template int resident_backward_as<LH_TILE, true>(size_t);
+#endif
+#if LH_BWD_UNIT != 1 && LH_TILE > LH_STAGE_RECOMPUTE_MAX_B
+template hipError_t launch_backward_as<LH_TILE, false>(const PersistArgs&, const cd*, cd*, cd*,
+                                                       const cd*, Partial*, int);
+template int resident_backward_as<LH_TILE, false>(size_t);
+#endif
 #elif LH_FAMILY == 2
 template <int B, int MODE>
 hipError_t launch_multi(const PersistArgs& a, const cd* ws, Partial* parts, int acc_dd,
