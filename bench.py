@@ -252,8 +252,8 @@ def main():
     tile = math.ceil(N / 8)
     fwd_kernel = f"forward_kernel<{tile}, {'true' if args.sum == 'et' else 'false'}>"
     # the backward instance the library selects: LDS-staged up to tile 5 when
-    # it reads the coefficient store, up to tile 4 when it recomputes them
-    staged = tile <= (5 if args.mode == "store" else 4)
+    # it reads the coefficient store, up to tile 3 when it recomputes them
+    staged = tile <= (5 if args.mode == "store" else 3)
     bwd_kernel = f"backward_kernel<{tile}, {'true' if staged else 'false'}>"
     fused = args.mode == "fused" and args.passes == "fwdbwd"
     if fused:

@@ -49,12 +49,13 @@ __host__ __device__ inline size_t bwd_item_elems(int B) {
 // one (one wavefront per SIMD, the operand and Krylov vectors in LDS) for
 // tiles up to kStageMaxB when the coefficients come from the store, but only
 // up to LH_STAGE_RECOMPUTE_MAX_B when the launch recomputes them (fused pass
-// or recomputing backward): there tile 5 runs unstaged at two wavefronts per
-// SIMD, whose second wavefront hides the latency of the term's spectral
-// phase (measured at N = 40: fused pass 4.47 vs 4.19 M terms/s; from the
-// store the staged instance stays ahead, 6.82 vs 5.51).
+// or recomputing backward): there tiles 4 and 5 run unstaged at two
+// wavefronts per SIMD, whose second wavefront hides the latency of the term's
+// spectral phase (measured fused pass: N = 40 4.47 vs 4.19, N = 32 7.92 vs
+// 6.95 M terms/s; three wavefronts at tile 4 6.71); from the store the
+// staged instance stays ahead (N = 40 6.82 vs 5.51).
 #ifndef LH_STAGE_RECOMPUTE_MAX_B
-#define LH_STAGE_RECOMPUTE_MAX_B 4
+#define LH_STAGE_RECOMPUTE_MAX_B 3
 #endif
 __host__ __device__ constexpr bool bwd_staged(int bmax, bool from_store) {
   return bmax <= (from_store ? kStageMaxB : LH_STAGE_RECOMPUTE_MAX_B);
@@ -214,7 +215,7 @@ __host__ __device__ constexpr int mul_group(int B) { return LH_MULG(B); }
 // terms/s).  Tile 8 keeps one row group at a time (two full accumulators do
 // not fit the register file).
 #ifndef LH_UNSTAGED_DPP
-#define LH_UNSTAGED_DPP(B) ((B) >= 5 && (B) <= 7)
+#define LH_UNSTAGED_DPP(B) ((B) >= 4 && (B) <= 7)
 #endif
 
 template <int B>
@@ -598,7 +599,7 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
 
 #ifndef LH_BWD_WAVES
 #define LH_BWD_WAVES(bmax, stg) \
-  ((bmax) <= 1 ? 4 : ((bmax) <= 3 ? 2 : ((bmax) == 5 && !(stg) ? 2 : 1)))
+  ((bmax) <= 1 ? 4 : ((bmax) <= 3 ? 2 : ((bmax) <= 5 && !(stg) ? 2 : 1)))
 #endif
 #ifndef LH_BWD_ATTR
 #define LH_BWD_ATTR                   \
