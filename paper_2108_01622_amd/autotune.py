@@ -71,7 +71,10 @@ def tune(sizes=(16, 24, 32, 40, 48, 56, 64), kinds=("et", "fds", "grad"), reps=2
                     api.lhaf_batched(A, g, **kw)
                 torch.cuda.synchronize()
                 times.append((time.perf_counter() - t) / reps)
-            k = int(np.argmin(times))
+            # the coarsest schedule within 2 % of the fastest: fewer, larger
+            # items also suit smaller inputs than the measured one, where
+            # finer cuts leave items of a few terms each
+            k = next(i for i, x in enumerate(times) if x <= 1.02 * min(times))
             best[(B, kind)] = k
             row = dict(N=N, B=B, kind=kind, batch=len(A_np), term_end=term_end, best=k,
                        times_ms=[round(1e3 * x, 3) for x in times])

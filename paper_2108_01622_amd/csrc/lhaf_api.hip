@@ -130,7 +130,7 @@ struct ProblemIn {
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t counter, probs, items, parts, aoff, goff, ioff, cdata, total;
+  size_t counter, probs, items, parts, parts2, aoff, goff, ioff, cdata, total;
 };
 
 Layout layout_for(int nprob, int nitems, size_t c_elems) {
@@ -143,6 +143,8 @@ Layout layout_for(int nprob, int nitems, size_t c_elems) {
   L.items = o;
   o = align_up(o + sizeof(Item) * (size_t)std::max(nitems, 1));
   L.parts = o;
+  o = align_up(o + sizeof(Partial) * (size_t)std::max(nitems, 1));
+  L.parts2 = o;  // partials of a second launch over the same items
   o = align_up(o + sizeof(Partial) * (size_t)std::max(nitems, 1));
   L.aoff = o;
   o = align_up(o + 8 * (size_t)std::max(nprob, 1));
@@ -387,6 +389,15 @@ using namespace lh;
 
 namespace lh {
 
+// ET sums over problems of tile > kEtSplitTile run as two launches over the
+// same items: the terms whose reduced tile is at most kEtSplitTile in that
+// tile's instance (more resident wavefronts), the others in the largest
+// tile's instance.
+constexpr int kEtSplitTile = 3;
+#ifndef LH_ET_SPLIT
+#define LH_ET_SPLIT 1
+#endif
+
 // Launch shape and plan tables of a persistent kernel over plan `pl`.
 static PersistArgs persist_args(const Plan& pl, char* base, size_t lds, hipStream_t st) {
   PersistArgs a;
@@ -422,14 +433,32 @@ lh_status run_forward(Plan& pl, const lh_c128* A, int64_t lda, const lh_c128* g,
   if (hipGetLastError() != hipSuccess) return LH_EHIP;
   const int acc_dd = o.acc == LH_ACC_DD ? 1 : 0;
   cd* sv = reinterpret_cast<cd*>(o.saved);
+  const Partial* parts2 = nullptr;
   if (!pl.items.empty()) {
-    const PersistArgs pa = persist_args(pl, base, lds_bytes_for(std::max(pl.nmax, 1)), st);
+    const size_t lds = lds_bytes_for(std::max(pl.nmax, 1));
+    PersistArgs pa = persist_args(pl, base, lds, st);
     const cd* wsc = reinterpret_cast<const cd*>(base + pl.lay.cdata);
     Partial* parts = reinterpret_cast<Partial*>(base + pl.lay.parts);
-    hipError_t e;
+    const int et = o.sum == LH_SUM_ET;
+    int tlo = 1;
+    hipError_t e = hipSuccess;
+    if (et && pl.bmax > kEtSplitTile && LH_ET_SPLIT) {
+      // ET terms of reduced tile <= kEtSplitTile in that tile's instance (more
+      // resident wavefronts), the rest below in the largest tile's
+      PersistArgs pa1 = pa;
+      pa1.grid = (int)std::min<int64_t>(
+          (int64_t)g_dev[dev].cus * std::max(1, resident_forward<kEtSplitTile>(lds, 1)),
+          std::max<int64_t>(1, (int64_t)pl.items.size()));
+      e = launch_forward<kEtSplitTile>(pa1, wsc, parts, acc_dd, sv, 1, 1, kEtSplitTile);
+      if (e != hipSuccess) return LH_EHIP;
+      pa.counter += kSecondCounter;
+      parts = reinterpret_cast<Partial*>(base + pl.lay.parts2);
+      parts2 = parts;
+      tlo = kEtSplitTile + 1;
+    }
     switch (pl.bmax) {
 #define LH_FCASE(BB) \
-  case BB: e = launch_forward<BB>(pa, wsc, parts, acc_dd, sv, o.sum == LH_SUM_ET); break;
+  case BB: e = launch_forward<BB>(pa, wsc, parts, acc_dd, sv, et, tlo, 8); break;
       LH_FCASE(1) LH_FCASE(2) LH_FCASE(3) LH_FCASE(4) LH_FCASE(5) LH_FCASE(6) LH_FCASE(7)
       default: LH_FCASE(8)
 #undef LH_FCASE
@@ -438,8 +467,8 @@ lh_status run_forward(Plan& pl, const lh_c128* A, int64_t lda, const lh_c128* g,
   }
   hipLaunchKernelGGL(finalize_kernel, dim3((nprob + 127) / 128), dim3(128), 0, st,
                      reinterpret_cast<const Prob*>(base + pl.lay.probs), nprob,
-                     reinterpret_cast<const Partial*>(base + pl.lay.parts), out, o.out_lo, err,
-                     acc_dd, 0);
+                     reinterpret_cast<const Partial*>(base + pl.lay.parts), parts2, out, o.out_lo,
+                     err, acc_dd, 0);
   if (hipGetLastError() != hipSuccess) return LH_EHIP;
   return LH_OK;
 }
@@ -921,8 +950,8 @@ static lh_status backward_impl(int32_t B, const lh_c128* A_base, int64_t lda, in
     if (hipGetLastError() != hipSuccess) return LH_EHIP;
     if (fused) {
       hipLaunchKernelGGL(finalize_kernel, dim3((nprob + 127) / 128), dim3(128), 0, st, probs,
-                         nprob, reinterpret_cast<const Partial*>(base + pl.lay.parts), out,
-                         o.out_lo, err_est, acc_dd, o.scaled ? 0 : 1);
+                         nprob, reinterpret_cast<const Partial*>(base + pl.lay.parts), nullptr,
+                         out, o.out_lo, err_est, acc_dd, o.scaled ? 0 : 1);
       return hipGetLastError() == hipSuccess ? LH_OK : LH_EHIP;
     }
   }

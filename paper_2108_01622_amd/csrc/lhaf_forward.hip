@@ -555,11 +555,15 @@ __device__ __forceinline__ cd term_f_at(const int bt, const cd* __restrict__ Cp,
 // term; otherwise every term runs at the problem's tile B = P.B.  (ET and
 // FDS batches are separate kernels: the per-term tile switch would raise the
 // register pressure of the FDS path.)
+// kET with tile bounds [tlo, thi]: only the terms whose reduced tile
+// ceil(2H'/8) lies in the bounds are evaluated (the ET term space split into
+// tile classes, each launched at its own occupancy; the classes' partial sums
+// add up).
 template <int B, bool kET>
 __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const int64_t t1,
                                          const cd* __restrict__ Cp, const cd* __restrict__ vp,
                                          Partial* __restrict__ out, LdsView& L, const int acc_dd,
-                                         cd* __restrict__ saved) {
+                                         cd* __restrict__ saved, const int tlo, const int thi) {
   const int lane0 = threadIdx.x & 63;
   const int m = P.m, H = P.H, n = P.n, LDp = 8 * P.B;
   int* km = reinterpret_cast<int*>(L.wv);  // free until the Hessenberg phase
@@ -574,6 +578,13 @@ __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const 
     LH_OPAQUE(LH_OPAQUE_TERM, lane);
     const int p = lane >> 3, q = lane & 7;
     if (t != t0) term_next(it, H, lane);
+    if constexpr (kET) {
+      const int hk = __popcll(__ballot(lane < H && it.digit != 0));
+      const int bt = (2 * hk + 7) >> 3;
+      // (a term needing a larger tile than this instance's belongs to the
+      // other launch of a split sum)
+      if (hk == 0 || bt < tlo || bt > thi || bt > B) continue;  // uniform: no LDS touched
+    }
     double coef;
     bool empty;
     const double wl = term_weight(it, P, lane, coef, empty);
@@ -666,7 +677,10 @@ __global__ void pack_kernel(const Prob* __restrict__ probs, const int64_t* __res
     }
     v[i] = val;
   }
-  if (b == 0 && threadIdx.x == 0) *counter = 0;
+  if (b == 0 && threadIdx.x == 0) {
+    counter[0] = 0;
+    counter[kSecondCounter] = 0;  // queue of a second launch over the same items
+  }
 }
 
 #endif  // LH_COMMON_KERNELS
@@ -682,7 +696,8 @@ __attribute__((amdgpu_waves_per_eu(LH_FWD_WAVES(BMAX), LH_FWD_WAVES(BMAX)))) voi
                                                      const Item* __restrict__ items, int n_items,
                                                      int* counter, const cd* __restrict__ ws,
                                                      Partial* __restrict__ parts, int acc_dd,
-                                                     int nmax, cd* __restrict__ saved) {
+                                                     int nmax, cd* __restrict__ saved, int tlo,
+                                                     int thi) {
   extern __shared__ __align__(16) char lds_raw[];
   LdsView L = carve(lds_raw, nmax);
   const int lane = threadIdx.x & 63;
@@ -699,13 +714,15 @@ __attribute__((amdgpu_waves_per_eu(LH_FWD_WAVES(BMAX), LH_FWD_WAVES(BMAX)))) voi
     const cd* Cp = ws + P.c_off;
     const cd* vp = Cp + LD * LD;
     if constexpr (kET) {
-      if (P.B <= BMAX) run_item<BMAX, true>(P, I.t0, I.t1, Cp, vp, parts + I.pad, L, acc_dd, saved);
+      // every problem: a term runs at its reduced tile, which the tile
+      // bounds keep within BMAX
+      run_item<BMAX, true>(P, I.t0, I.t1, Cp, vp, parts + I.pad, L, acc_dd, saved, tlo, thi);
     } else {
       switch (P.B) {
 #define LH_CASE(BB)                                                                       \
   case BB:                                                                                \
     if constexpr (BB <= BMAX)                                                             \
-      run_item<BB, false>(P, I.t0, I.t1, Cp, vp, parts + I.pad, L, acc_dd, saved);        \
+      run_item<BB, false>(P, I.t0, I.t1, Cp, vp, parts + I.pad, L, acc_dd, saved, 1, 8);  \
     break;
         LH_CASE(1) LH_CASE(2) LH_CASE(3) LH_CASE(4) LH_CASE(5) LH_CASE(6) LH_CASE(7) LH_CASE(8)
 #undef LH_CASE
@@ -720,8 +737,11 @@ __attribute__((amdgpu_waves_per_eu(LH_FWD_WAVES(BMAX), LH_FWD_WAVES(BMAX)))) voi
 // Sum the item partials of each problem in item order (double-double),
 // apply the FDS prefactor and write the result and an error estimate.
 // With `raw` the prefactor is not applied (partial sums of a term range).
+// parts2 (nullable): the partials of a second launch over the same items
+// (the other tile class of a split ET sum), added after the first set.
 __global__ void finalize_kernel(const Prob* __restrict__ probs, int nprob,
-                                const Partial* __restrict__ parts, lh_c128* out, lh_c128* out_lo,
+                                const Partial* __restrict__ parts,
+                                const Partial* __restrict__ parts2, lh_c128* out, lh_c128* out_lo,
                                 double* err, int acc_dd, int raw) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nprob) return;
@@ -732,11 +752,14 @@ __global__ void finalize_kernel(const Prob* __restrict__ probs, int nprob,
     sr.hi = 1.0;
     sabs = 1.0;
   }
-  for (int k = 0; k < P.n_items; ++k) {
-    const Partial pr = parts[P.first_item + k];
-    dd_add(sr, pr.hr, pr.lr);
-    dd_add(si, pr.hi, pr.li);
-    sabs += pr.abs_sum;
+  for (int set = 0; set < (parts2 ? 2 : 1); ++set) {
+    const Partial* ps = set == 0 ? parts : parts2;
+    for (int k = 0; k < P.n_items; ++k) {
+      const Partial pr = ps[P.first_item + k];
+      dd_add(sr, pr.hr, pr.lr);
+      dd_add(si, pr.hi, pr.li);
+      sabs += pr.abs_sum;
+    }
   }
   const double sc = raw ? 1.0 : P.scale;  // power of two: exact
   sr.hi *= sc;

@@ -50,6 +50,10 @@ __host__ __device__ inline int64_t lh_longest_item(const Prob& P) {
   return (P.t1 - P.t0 + k - 1) / k;
 }
 
+// Offset (ints) of the work counter of a second launch over the same items,
+// on its own cache line in the 256-byte counter block of the workspace.
+constexpr int kSecondCounter = 32;
+
 // Partial sum of one item: double-double complex + sum of |c_t f_t|.
 struct Partial {
   double hr, hi, lr, li, abs_sum, pad0, pad1, pad2;

@@ -26,10 +26,11 @@ struct PersistArgs {
 };
 
 // forward_kernel<B, et>: item partials (and the per-term coefficient store);
-// et selects the ET instance (per-term tiles with pair deletion)
+// et selects the ET instance (per-term tiles with pair deletion), which
+// evaluates only the terms whose reduced tile lies in [tlo, thi]
 template <int B>
 hipError_t launch_forward(const PersistArgs& a, const cd* ws, Partial* parts, int acc_dd,
-                          cd* saved, int et);
+                          cd* saved, int et, int tlo, int thi);
 // backward_kernel<B>: item gradient slots; per-wavefront scratch; with
 // `parts` (fused pass) also the item partials of the value
 template <int B, bool kStg>

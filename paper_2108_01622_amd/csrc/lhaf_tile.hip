@@ -51,15 +51,15 @@ namespace lh {
 #if LH_FAMILY == 0
 template <int B>
 hipError_t launch_forward(const PersistArgs& a, const cd* ws, Partial* parts, int acc_dd,
-                          cd* saved, int et) {
+                          cd* saved, int et, int tlo, int thi) {
   if (et)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(forward_kernel<B, true>), dim3(a.grid), dim3(64), a.lds,
                        a.stream, a.probs, a.items, a.n_items, a.counter, ws, parts, acc_dd, a.nmax,
-                       saved);
+                       saved, tlo, thi);
   else
     hipLaunchKernelGGL(HIP_KERNEL_NAME(forward_kernel<B, false>), dim3(a.grid), dim3(64), a.lds,
                        a.stream, a.probs, a.items, a.n_items, a.counter, ws, parts, acc_dd, a.nmax,
-                       saved);
+                       saved, 1, 8);
   return hipGetLastError();
 }
 template <int B>
@@ -71,7 +71,7 @@ int resident_forward(size_t lds, int et) {
   return blocks;
 }
 template hipError_t launch_forward<LH_TILE>(const PersistArgs&, const cd*, Partial*, int, cd*,
-                                            int);
+                                            int, int, int);
 template int resident_forward<LH_TILE>(size_t, int);
 #elif LH_FAMILY == 1
 // LH_BWD_UNIT: 0 every instance of the tile, 1 the LDS-staged one only, 2 the
