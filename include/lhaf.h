@@ -68,10 +68,20 @@ typedef int32_t lh_status;
 #define LH_SUM_FDS 1 /* finite-difference sieve (App. B.4), sign-halved */
 #define LH_ACC_FP64 0 /* plain double accumulation of the signed term sum */
 #define LH_ACC_DD 1   /* double-double (TwoProd/TwoSum) accumulation */
+/* LH_ACC_DD_COMP: double-double accumulation, and every term's characteristic
+   polynomial (the cofactor recurrence on its Hessenberg form), the two
+   power-series recurrences and the final lambda^n coefficient formed
+   as compensated dot products (each value as if computed in twice the working
+   precision and rounded once; Ogita, Rump and Oishi 2005).  About ten times
+   smaller per-term error on ill-conditioned terms, at a higher cost per term.
+   Values only: lhaf, lhaf_repeated, lhaf_batched (not fused, no saved),
+   lhaf_batched_noalloc and lhaf_mixed; the other entry points return
+   LH_EUNSUPPORTED.  err_est is the same a-priori estimate as for LH_ACC_DD. */
+#define LH_ACC_DD_COMP 2
 
 typedef struct {
   int32_t sum;        /* LH_SUM_FDS (default) or LH_SUM_ET */
-  int32_t acc;        /* LH_ACC_DD (default) or LH_ACC_FP64 */
+  int32_t acc;        /* LH_ACC_DD (default), LH_ACC_FP64 or LH_ACC_DD_COMP */
   int64_t term_begin; /* first term of the enumeration to include (default 0) */
   int64_t term_end;   /* one past the last term, -1 = all (default) */
   int32_t scaled;     /* 1 (default): out = lhaf.  0: out = raw partial sum over

@@ -14,10 +14,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LHAF_LIBRARY") or os.path.join(_HERE, "_lib", "liblhaf.so")
 
 LH_SUM_ET, LH_SUM_FDS = 0, 1
-LH_ACC_FP64, LH_ACC_DD = 0, 1
+LH_ACC_FP64, LH_ACC_DD, LH_ACC_DD_COMP = 0, 1, 2
 
 _SUMS = {"et": LH_SUM_ET, "fds": LH_SUM_FDS}
-_ACCS = {"fp64": LH_ACC_FP64, "dd": LH_ACC_DD}
+# "ddc": double-double accumulation with compensated per-term recurrences
+# (values only: lhaf, repeated, batched without saved/grads, noalloc, mixed)
+_ACCS = {"fp64": LH_ACC_FP64, "dd": LH_ACC_DD, "ddc": LH_ACC_DD_COMP}
 
 
 class LhOpts(ctypes.Structure):

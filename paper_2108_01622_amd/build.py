@@ -28,7 +28,9 @@ OBJDIR = os.path.join(ROOT, "_build", "lhaf")
 LIB = os.path.join(LIBDIR, "liblhaf.so")
 ARCH = os.environ.get("LHAF_OFFLOAD_ARCH", "gfx950")
 
-FAMILIES = {0: "lhaf_forward.hip", 1: "lhaf_backward.hip", 2: "lhaf_multi.hip", 3: "lhaf_real.hip"}
+# family 4: the forward with compensated recurrences (its kernels are in lhaf_forward.hip)
+FAMILIES = {0: "lhaf_forward.hip", 1: "lhaf_backward.hip", 2: "lhaf_multi.hip", 3: "lhaf_real.hip",
+            4: "lhaf_forward.hip"}
 TILES = range(1, 9)
 BWD_SPLIT_TILES = (4, 5)  # backward tiles with a staged and an unstaged instance
 _COMMON = ["lhaf.h", "lhaf_device.h", "lhaf_internal.h", "lhaf_forward.hip", "lhaf_launch.h"]

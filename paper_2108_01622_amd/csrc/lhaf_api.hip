@@ -431,11 +431,14 @@ lh_status run_forward(Plan& pl, const lh_c128* A, int64_t lda, const lh_c128* g,
                      reinterpret_cast<cd*>(base + pl.lay.cdata),
                      reinterpret_cast<int*>(base + pl.lay.counter));
   if (hipGetLastError() != hipSuccess) return LH_EHIP;
-  const int acc_dd = o.acc == LH_ACC_DD ? 1 : 0;
+  // 0 plain FP64, 1 double-double accumulation (also with compensated recurrences)
+  const int acc_dd = o.acc == LH_ACC_FP64 ? 0 : 1;
+  const bool comp = o.acc == LH_ACC_DD_COMP;
   cd* sv = reinterpret_cast<cd*>(o.saved);
   const Partial* parts2 = nullptr;
   if (!pl.items.empty()) {
-    const size_t lds = lds_bytes_for(std::max(pl.nmax, 1));
+    const size_t lds = comp ? lds_bytes_comp(std::max(pl.nmax, 1))
+                            : lds_bytes_for(std::max(pl.nmax, 1));
     PersistArgs pa = persist_args(pl, base, lds, st);
     const cd* wsc = reinterpret_cast<const cd*>(base + pl.lay.cdata);
     Partial* parts = reinterpret_cast<Partial*>(base + pl.lay.parts);
@@ -447,9 +450,12 @@ lh_status run_forward(Plan& pl, const lh_c128* A, int64_t lda, const lh_c128* g,
       // resident wavefronts), the rest below in the largest tile's
       PersistArgs pa1 = pa;
       pa1.grid = (int)std::min<int64_t>(
-          (int64_t)g_dev[dev].cus * std::max(1, resident_forward<kEtSplitTile>(lds, 1)),
+          (int64_t)g_dev[dev].cus *
+              std::max(1, comp ? resident_forward_comp<kEtSplitTile>(lds, 1)
+                               : resident_forward<kEtSplitTile>(lds, 1)),
           std::max<int64_t>(1, (int64_t)pl.items.size()));
-      e = launch_forward<kEtSplitTile>(pa1, wsc, parts, acc_dd, sv, 1, 1, kEtSplitTile);
+      e = comp ? launch_forward_comp<kEtSplitTile>(pa1, wsc, parts, acc_dd, sv, 1, 1, kEtSplitTile)
+               : launch_forward<kEtSplitTile>(pa1, wsc, parts, acc_dd, sv, 1, 1, kEtSplitTile);
       if (e != hipSuccess) return LH_EHIP;
       pa.counter += kSecondCounter;
       parts = reinterpret_cast<Partial*>(base + pl.lay.parts2);
@@ -458,7 +464,10 @@ lh_status run_forward(Plan& pl, const lh_c128* A, int64_t lda, const lh_c128* g,
     }
     switch (pl.bmax) {
 #define LH_FCASE(BB) \
-  case BB: e = launch_forward<BB>(pa, wsc, parts, acc_dd, sv, et, tlo, 8); break;
+  case BB:                                                                   \
+    e = comp ? launch_forward_comp<BB>(pa, wsc, parts, acc_dd, sv, et, tlo, 8) \
+             : launch_forward<BB>(pa, wsc, parts, acc_dd, sv, et, tlo, 8);     \
+    break;
       LH_FCASE(1) LH_FCASE(2) LH_FCASE(3) LH_FCASE(4) LH_FCASE(5) LH_FCASE(6) LH_FCASE(7)
       default: LH_FCASE(8)
 #undef LH_FCASE
@@ -591,11 +600,14 @@ static lh_status parse_problems(int32_t B, const int64_t* idx_off, const int32_t
   return LH_OK;
 }
 
-static lh_status validate_opts(const lh_opts* opts, lh_opts& o) {
+// comp_ok: the entry point evaluates values through the forward kernels, the
+// only ones with a compensated-recurrence instance
+static lh_status validate_opts(const lh_opts* opts, lh_opts& o, bool comp_ok = false) {
   lh_opts_default(&o);
   if (opts) o = *opts;
   if (o.sum != LH_SUM_ET && o.sum != LH_SUM_FDS) return LH_EINVAL;
-  if (o.acc != LH_ACC_FP64 && o.acc != LH_ACC_DD) return LH_EINVAL;
+  if (o.acc != LH_ACC_FP64 && o.acc != LH_ACC_DD && o.acc != LH_ACC_DD_COMP) return LH_EINVAL;
+  if (o.acc == LH_ACC_DD_COMP && (!comp_ok || o.saved || o.grads)) return LH_EUNSUPPORTED;
   if (o.saved && o.saved_count < 0) return LH_EINVAL;
   if (o.grads && o.grads_count < 0) return LH_EINVAL;
   return LH_OK;
@@ -670,7 +682,7 @@ static lh_status batched_impl(int32_t B, const lh_c128* A_base, int64_t lda, int
 size_t lhaf_batched_workspace(int32_t B, const int64_t* idx_off, const int32_t* r,
                               const lh_opts* opts) {
   lh_opts o;
-  if (validate_opts(opts, o) != LH_OK) return 0;
+  if (validate_opts(opts, o, true) != LH_OK) return 0;
   size_t need = 0;
   if (batched_impl(B, nullptr, 1, 0, nullptr, 0, nullptr, idx_off, r, nullptr, nullptr, nullptr,
                    0, o, nullptr, true, &need) != LH_OK)
@@ -683,7 +695,7 @@ lh_status lhaf_batched(int32_t B, const lh_c128* A_base, int64_t lda, int64_t st
                        const int64_t* idx_off, const int32_t* r, lh_c128* out, double* err_est,
                        void* workspace, size_t ws_bytes, const lh_opts* opts, void* stream) {
   lh_opts o;
-  lh_status s = validate_opts(opts, o);
+  lh_status s = validate_opts(opts, o, true);
   if (s != LH_OK) return s;
   if (workspace == nullptr && o.workspace) {
     workspace = o.workspace;
@@ -698,7 +710,7 @@ lh_status lhaf_batched_noalloc(int32_t B, const lh_c128* A_base, int64_t lda, in
                                const int64_t* idx_off, const int32_t* r, lh_c128* out,
                                double* err_est, const lh_opts* opts, void* stream) {
   lh_opts o;
-  lh_status s = validate_opts(opts, o);
+  lh_status s = validate_opts(opts, o, true);
   if (s != LH_OK) return s;
   if (o.grads) return LH_EUNSUPPORTED;
   std::vector<ProblemIn> pin;
@@ -726,7 +738,7 @@ size_t lhaf_noalloc_scratch_bytes(void) { return kStaticScratchBytes; }
 lh_status lhaf(const lh_c128* A, int64_t lda, const lh_c128* gamma, int32_t N, lh_c128* out,
                double* err_est, const lh_opts* opts, void* stream) {
   lh_opts o;
-  lh_status s = validate_opts(opts, o);
+  lh_status s = validate_opts(opts, o, true);
   if (s != LH_OK) return s;
   if (N < 0 || !out) return LH_EINVAL;
   if (N > kMaxN) return LH_ESIZE;
@@ -748,7 +760,7 @@ lh_status lhaf_repeated(const lh_c128* A, int64_t lda, const lh_c128* gamma, con
                         int32_t M, lh_c128* out, double* err_est, const lh_opts* opts,
                         void* stream) {
   lh_opts o;
-  lh_status s = validate_opts(opts, o);
+  lh_status s = validate_opts(opts, o, true);
   if (s != LH_OK) return s;
   if (M < 0 || !out || (M > 0 && !r)) return LH_EINVAL;
   int64_t tot = 0;
@@ -972,7 +984,7 @@ static lh_status backward_impl(int32_t B, const lh_c128* A_base, int64_t lda, in
 lh_status lhaf_mixed(const lh_c128* A, int64_t lda, const lh_c128* gamma, const int32_t* n,
                      int32_t M, lh_c128* out, double* err_est, const lh_opts* opts, void* stream) {
   lh_opts o;
-  lh_status s = validate_opts(opts, o);
+  lh_status s = validate_opts(opts, o, true);
   if (s != LH_OK) return s;
   if (M < 0 || !out || (M > 0 && !n)) return LH_EINVAL;
   int64_t tot = 0;

@@ -253,11 +253,150 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // ---------------------------------------------------------------------------
-// double-double accumulation (Knuth TwoSum, FMA TwoProd)
+// Double-double complex values for the compensated-recurrence mode: a complex
+// value as unevaluated sums hi + lo per component.  cdd_fma adds a * b with
+// every real product split exactly (FMA TwoProd) and every addition to the
+// high parts exact (Knuth TwoSum), the rounding errors gathered in the low
+// parts, so a dot product comes out as if formed in twice the working
+// precision (the compensated dot product of Ogita, Rump and Oishi, 2005);
+// cdd_fma_hl / cdd_fma_hl2 take double-double operands (their low-part
+// cross products in plain FP64: relative error O(u^2)), and cdd_split
+// renormalises a result into the (hi, lo) pair that is stored.
+struct cdd {
+  double rh, rl, ih, il;
+};
+__device__ __forceinline__ cdd cdd_zero() { return {0.0, 0.0, 0.0, 0.0}; }
+__device__ __forceinline__ cdd cdd_of(const cd a) { return {a.r, 0.0, a.i, 0.0}; }
+__device__ __forceinline__ cdd cdd_neg(const cdd a) { return {-a.rh, -a.rl, -a.ih, -a.il}; }
+// s + e = a + b exactly (Knuth's TwoSum; the same bits for either order).
+// The error-free transformations here and below turn off floating-point
+// contraction: HIP contracts a product into a later addition by default,
+// which would fuse x * y into the TwoSum of a TwoProd and count the
+// product's rounding error twice.
+__device__ __forceinline__ void two_sum(const double a, const double b, double& s, double& e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+// h + l += x * y
+__device__ __forceinline__ void dd_acc_prod(double& h, double& l, const double x, const double y) {
+#pragma clang fp contract(off)
+  const double p = x * y;
+  const double pe = fma(x, y, -p);
+  double s, e;
+  two_sum(h, p, s, e);
+  h = s;
+  l += e + pe;
+}
+// acc += a * b
+__device__ __forceinline__ void cdd_fma(cdd& acc, const cd a, const cd b) {
+  dd_acc_prod(acc.rh, acc.rl, a.r, b.r);
+  dd_acc_prod(acc.rh, acc.rl, -a.i, b.i);
+  dd_acc_prod(acc.ih, acc.il, a.r, b.i);
+  dd_acc_prod(acc.ih, acc.il, a.i, b.r);
+}
+// a + b; commutative to the bit, so two lanes that combine each other's
+// values end with the same bits
+__device__ __forceinline__ cdd cdd_plus(const cdd& a, const cdd& b) {
+  cdd r;
+  double e;
+  two_sum(a.rh, b.rh, r.rh, e);
+  r.rl = e + (a.rl + b.rl);
+  two_sum(a.ih, b.ih, r.ih, e);
+  r.il = e + (a.il + b.il);
+  return r;
+}
+__device__ __forceinline__ cd cdd_round(const cdd& a) { return mk(a.rh + a.rl, a.ih + a.il); }
+// acc += a * (bh + bl)
+__device__ __forceinline__ void cdd_fma_hl(cdd& acc, const cd a, const cd bh, const cd bl) {
+  cdd_fma(acc, a, bh);
+  acc.rl += fma(a.r, bl.r, -a.i * bl.i);
+  acc.il += fma(a.r, bl.i, a.i * bl.r);
+}
+// acc += (ah + al) * (bh + bl)
+__device__ __forceinline__ void cdd_fma_hl2(cdd& acc, const cd ah, const cd al, const cd bh,
+                                            const cd bl) {
+  cdd_fma(acc, ah, bh);
+  acc.rl += fma(ah.r, bl.r, -ah.i * bl.i) + fma(al.r, bh.r, -al.i * bh.i);
+  acc.il += fma(ah.r, bl.i, ah.i * bl.r) + fma(al.r, bh.i, al.i * bh.r);
+}
+// (h + l) / k for a small positive integer k: the quotient of the high part,
+// corrected by its exact remainder and the low part
+__device__ __forceinline__ void dd_div(double& h, double& l, const double k) {
+  const double q = h / k;
+  const double r = fma(-q, k, h);
+  h = q;
+  l = (r + l) / k;
+}
+__device__ __forceinline__ cdd cdd_div(cdd a, const double k) {
+  dd_div(a.rh, a.rl, k);
+  dd_div(a.ih, a.il, k);
+  return a;
+}
+// renormalised (hi, lo): hi = fl(hi + lo), lo the exact remainder (TwoSum:
+// after a cancellation the low part can exceed the high one)
+__device__ __forceinline__ void cdd_split(const cdd& a, cd& hi, cd& lo) {
+  two_sum(a.rh, a.rl, hi.r, lo.r);
+  two_sum(a.ih, a.il, hi.i, lo.i);
+}
+// a + (a of another lane) for the lane patterns of the plain sums above; the
+// permlane swaps hand every lane of a pair its two values in the same order
+template <int CTRL>
+__device__ __forceinline__ cdd cdd_plus_dpp(const cdd& a) {
+  return cdd_plus(a, {dpp_d<CTRL>(a.rh), dpp_d<CTRL>(a.rl), dpp_d<CTRL>(a.ih), dpp_d<CTRL>(a.il)});
+}
+__device__ __forceinline__ void swap16_d(const double x, double& v0, double& v1) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  auto L = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  auto H = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  v0 = __hiloint2double(H[0], L[0]);
+  v1 = __hiloint2double(H[1], L[1]);
+}
+__device__ __forceinline__ void swap32_d(const double x, double& v0, double& v1) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  auto L = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  auto H = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  v0 = __hiloint2double(H[0], L[0]);
+  v1 = __hiloint2double(H[1], L[1]);
+}
+__device__ __forceinline__ cdd cdd_plus_xor16(const cdd& a) {
+  cdd u, v;
+  swap16_d(a.rh, u.rh, v.rh);
+  swap16_d(a.rl, u.rl, v.rl);
+  swap16_d(a.ih, u.ih, v.ih);
+  swap16_d(a.il, u.il, v.il);
+  return cdd_plus(u, v);
+}
+__device__ __forceinline__ cdd cdd_plus_xor32(const cdd& a) {
+  cdd u, v;
+  swap32_d(a.rh, u.rh, v.rh);
+  swap32_d(a.rl, u.rl, v.rl);
+  swap32_d(a.ih, u.ih, v.ih);
+  swap32_d(a.il, u.il, v.il);
+  return cdd_plus(u, v);
+}
+// compensated sums over the row group, each half-wave and the whole wave
+__device__ __forceinline__ cdd cdd_sum_row8(cdd a) {
+  a = cdd_plus_dpp<0xB1>(a);   // quad_perm [1,0,3,2]
+  a = cdd_plus_dpp<0x4E>(a);   // quad_perm [2,3,0,1]
+  return cdd_plus_dpp<0x141>(a);  // row_half_mirror
+}
+__device__ __forceinline__ cdd cdd_sum_half32(cdd a) {
+  a = cdd_sum_row8(a);
+  a = cdd_plus_dpp<0x128>(a);  // row_ror:8
+  return cdd_plus_xor16(a);
+}
+__device__ __forceinline__ cdd cdd_sum_wave(const cdd& a) { return cdd_plus_xor32(cdd_sum_half32(a)); }
+
+// ---------------------------------------------------------------------------
+// double-double accumulation (Knuth TwoSum, FMA TwoProd; no contraction, see
+// two_sum)
 struct dd {
   double hi, lo;
 };
 __device__ __forceinline__ void dd_add_prod(dd& acc, double c, double x) {
+#pragma clang fp contract(off)
   double p = c * x;
   double pe = fma(c, x, -p);
   double s = acc.hi + p;
@@ -269,6 +408,7 @@ __device__ __forceinline__ void dd_add_prod(dd& acc, double c, double x) {
   acc.hi = h2;
 }
 __device__ __forceinline__ void dd_add(dd& acc, double hi, double lo) {
+#pragma clang fp contract(off)
   double s = acc.hi + hi;
   double bb = s - acc.hi;
   double e = (acc.hi - (s - bb)) + (hi - bb);

@@ -33,6 +33,10 @@ struct LdsView {
   cd* mu;      // [33] loop moments
   cd* ser;     // [2][33] q / L series
   cd* ring;    // [NR][NP] characteristic polynomials of leading blocks
+  // compensated-recurrence instances only (beyond lds_bytes_for): the low
+  // parts of the ring's and the series' double-double values
+  cd* ring_lo;  // [NR][NP]
+  cd* ser_lo;   // [2][33]
   int NP, NR;
 };
 
@@ -50,6 +54,8 @@ __device__ inline LdsView carve(char* base, int nmax) {
   L.ring = reinterpret_cast<cd*>(L.sc + 8);
   L.NP = nmax + 1;
   L.NR = nmax + 2;
+  L.ring_lo = L.ring + L.NP * L.NR;
+  L.ser_lo = L.ring_lo + L.NP * L.NR;
   return L;
 }
 
@@ -184,7 +190,9 @@ __device__ __forceinline__ void householder_step(double (&Wr)[B][B], double (&Wi
 //   T_J = (1 - lambda h_JJ) T_{J-1}
 //         - sum_{i<J} h_iJ (prod_{l=i+1..J} h_{l,l-1}) lambda^{J-i+1} T_{i-1}
 // (cofactor expansion along the last column), T_{-1} = 1.
-template <int B, int kb>
+// kComp: every new coefficient is a compensated dot product (formed as in
+// twice the working precision, rounded once when stored).
+template <int B, int kb, bool kComp = false>
 __device__ __forceinline__ void charpoly_step(const double (&Wr)[B][B], const double (&Wi)[B][B],
                                               const int jj, const int J, const int p, const int q,
                                               const int lane, const int n, cd& pi, cd& hsub,
@@ -205,6 +213,47 @@ __device__ __forceinline__ void charpoly_step(const double (&Wr)[B][B], const do
   wave_sync();
   const int t = (lane & 31) + 1;
   const int slot = lane >> 5;
+  if constexpr (kComp) {
+    // the ring holds double-double values (high parts in ring, low parts in
+    // ring_lo); each new coefficient is formed from them exactly up to a
+    // relative u^2 and kept unrounded
+    const cd* Rl = L.ring_lo;
+    cdd acc = cdd_zero(), acc2 = cdd_zero();
+    if (t <= n) {
+      const int ilo = (J + 1 - t) > 0 ? (J + 1 - t) : 0;
+      int i = J - 1 - slot;
+      for (; i - 2 >= ilo; i -= 4) {
+        const int o1 = ring_slot(i - 1, L.NR) * L.NP + t - (J - i + 1);
+        const int o2 = ring_slot(i - 3, L.NR) * L.NP + t - (J - i + 3);
+        cdd_fma_hl(acc, L.wb[i], L.ring[o1], Rl[o1]);
+        cdd_fma_hl(acc2, L.wb[i - 2], L.ring[o2], Rl[o2]);
+      }
+      if (i >= ilo) {
+        const int o1 = ring_slot(i - 1, L.NR) * L.NP + t - (J - i + 1);
+        cdd_fma_hl(acc, L.wb[i], L.ring[o1], Rl[o1]);
+      }
+    }
+    acc = cdd_plus_xor32(cdd_plus(acc, acc2));
+    const int op = ring_slot(J - 1, L.NR) * L.NP, oc = ring_slot(J, L.NR) * L.NP;
+    cd vh = czero(), vl = czero();
+    if (slot == 0 && t <= n) {
+      cdd v = {L.ring[op + t].r, Rl[op + t].r, L.ring[op + t].i, Rl[op + t].i};
+      cdd_fma_hl(v, mk(-hJJ.r, -hJJ.i), L.ring[op + t - 1], Rl[op + t - 1]);
+      cdd_split(cdd_plus(v, cdd_neg(acc)), vh, vl);
+    }
+    wave_sync();
+    if (slot == 0 && t <= n) {
+      L.ring[oc + t] = vh;
+      L.ring_lo[oc + t] = vl;
+    }
+    if (lane == 32) {
+      L.ring[oc] = mk(1.0, 0.0);
+      L.ring_lo[oc] = czero();
+    }
+    wave_sync();
+    hsub = hnext;
+    return;
+  }
   cd acc = czero(), acc2 = czero();
   if (t <= n) {
     const int ilo = (J + 1 - t) > 0 ? (J + 1 - t) : 0;
@@ -236,7 +285,7 @@ __device__ __forceinline__ void charpoly_step(const double (&Wr)[B][B], const do
 // -------------------------------------------------------------------------
 // Column blocks of 8: block KB is a compile-time constant, so every register
 // index stays static while the 8 steps inside a block run as a loop.
-template <int B, int KB>
+template <int B, int KB, bool kComp = false>
 struct HessLoop {
   __device__ __forceinline__ static void run(double (&Wr)[B][B], double (&Wi)[B][B], const int m,
                                              const int n, const int p, const int q,
@@ -250,13 +299,13 @@ struct HessLoop {
       LH_OPAQUE(LH_OPAQUE_STEP, ln);
       const int pp = ln >> 3, qq = ln & 7;
       if (j <= m - 3) householder_step<B, KB>(Wr, Wi, jj, j, pp, qq, L);
-      charpoly_step<B, KB>(Wr, Wi, jj, j, pp, qq, ln, n, pi, hsub, L);
+      charpoly_step<B, KB, kComp>(Wr, Wi, jj, j, pp, qq, ln, n, pi, hsub, L);
     }
-    HessLoop<B, KB + 1>::run(Wr, Wi, m, n, p, q, lane, pi, hsub, L);
+    HessLoop<B, KB + 1, kComp>::run(Wr, Wi, m, n, p, q, lane, pi, hsub, L);
   }
 };
-template <int B>
-struct HessLoop<B, B> {
+template <int B, bool kComp>
+struct HessLoop<B, B, kComp> {
   __device__ __forceinline__ static void run(double (&)[B][B], double (&)[B][B], const int,
                                              const int, const int, const int, const int, cd&,
                                              cd&, LdsView&) {}
@@ -408,20 +457,55 @@ __device__ __forceinline__ void loop_moments(const double (&Wr)[B][B], const dou
 // c(lambda) = det(I - lambda W); al = 0 gives y = exp(sum_j x_j lambda^j / 2).
 // Step k is a 32-lane dot product over j = 1..k (lane j-1 of the half)
 // reduced by a butterfly inside the half, so the serial chain is n steps.
+// kComp: each step is a compensated dot product (the weight al k + j/2 is
+// exact, its product with x_j is split exactly, and the sum is rounded once
+// after the division by k).
+// (x0_lo, y0_lo, y1_lo: the low parts of the double-double values, used by
+// the kComp instance only; x1 has none)
+template <bool kComp = false>
 __device__ __forceinline__ void two_series(const cd* x0, cd* y0, const double al0, const cd* x1,
-                                           cd* y1, const double al1, const int n, const int lane) {
+                                           cd* y1, const double al1, const int n, const int lane,
+                                           const cd* x0_lo = nullptr, cd* y0_lo = nullptr,
+                                           cd* y1_lo = nullptr) {
   const int h = lane >> 5, j = (lane & 31) + 1;
   const cd* xs = h == 0 ? x0 : x1;
   cd* ys = h == 0 ? y0 : y1;
   const cd xj = j <= n ? xs[j] : czero();
   const double al = h == 0 ? al0 : al1;
   if ((lane & 31) == 0) ys[0] = mk(1.0, 0.0);
+  [[maybe_unused]] cd* ys_lo = nullptr;
+  [[maybe_unused]] cd xjl = czero();
+  if constexpr (kComp) {
+    ys_lo = h == 0 ? y0_lo : y1_lo;
+    if (h == 0 && j <= n) xjl = x0_lo[j];
+    if ((lane & 31) == 0) ys_lo[0] = czero();
+  }
   wave_sync();
   for (int k = 1; k <= n; ++k) {
-    cd t = czero();
-    if (j <= k) t = cmul(cscale(fma(al, (double)k, 0.5 * j), xj), ys[k - j]);
-    t = sum_half32(t);
-    if ((lane & 31) == 0) ys[k] = cscale(1.0 / k, t);
+    if constexpr (kComp) {
+      // x and y double-double (x1 = the loop moments, exact in double); the
+      // weight al k + j/2 is exact and its product with x_j is split exactly
+      cdd t = cdd_zero();
+      if (j <= k) {
+        const double w = fma(al, (double)k, 0.5 * j);
+        const cd yh = ys[k - j], yl = ys_lo[k - j];
+        const cd wx = mk(w * xj.r, w * xj.i);
+        const cd wxl = mk(fma(w, xj.r, -wx.r) + w * xjl.r, fma(w, xj.i, -wx.i) + w * xjl.i);
+        cdd_fma_hl2(t, wx, wxl, yh, yl);
+      }
+      t = cdd_sum_half32(t);
+      if ((lane & 31) == 0) {
+        cd qh, ql;
+        cdd_split(cdd_div(t, (double)k), qh, ql);
+        ys[k] = qh;
+        ys_lo[k] = ql;
+      }
+    } else {
+      cd t = czero();
+      if (j <= k) t = cmul(cscale(fma(al, (double)k, 0.5 * j), xj), ys[k - j]);
+      t = sum_half32(t);
+      if ((lane & 31) == 0) ys[k] = cscale(1.0 / k, t);
+    }
     wave_sync();
   }
 }
@@ -431,16 +515,20 @@ __device__ __forceinline__ void two_series(const cd* x0, cd* y0, const double al
 // M = sum_k mu_k lambda^k / 2:
 //   L.ser[0..n]      q_k, k q_k = -sum_{j=1..k} (k - j/2) c_j q_{k-j}
 //   L.ser[33..33+n]  L_k, k L_k = sum_{j=1..k} (j/2) mu_j L_{k-j}
-template <int B>
+template <int B, bool kComp = false>
 __device__ __forceinline__ void spectral_series(double (&Wr)[B][B], double (&Wi)[B][B],
                                                 const int m, const int n, const int p,
                                                 const int q, const int lane, LdsView& L) {
   if (lane <= n) L.ring[lane] = lane == 0 ? mk(1.0, 0.0) : czero();  // T_{-1} in slot 0
+  if constexpr (kComp) {
+    if (lane <= n) L.ring_lo[lane] = czero();
+  }
   wave_sync();
   cd pi = czero(), hsub = czero();
-  HessLoop<B, 0>::run(Wr, Wi, m, n, p, q, lane, pi, hsub, L);
-  const cd* cpoly = L.ring + ring_slot(m - 1, L.NR) * L.NP;
-  two_series(cpoly, L.ser, -1.0, L.mu, L.ser + 33, 0.0, n, lane);
+  HessLoop<B, 0, kComp>::run(Wr, Wi, m, n, p, q, lane, pi, hsub, L);
+  const int co = ring_slot(m - 1, L.NR) * L.NP;
+  two_series<kComp>(L.ring + co, L.ser, -1.0, L.mu, L.ser + 33, 0.0, n, lane, L.ring_lo + co,
+                    L.ser_lo, L.ser_lo + 33);
 }
 
 // Lane k (1 <= k <= n): a_k = e_{n-k} / 2, where e_j = sum_{i<=j} q_i L_{j-i}
@@ -483,7 +571,7 @@ __device__ __forceinline__ int kept_map(const TermIter& it, const int H, const i
 // One term at register tile b: W = C X (every pair, or through km only the
 // kept pairs of an ET term), loop moments and the two series into L.ser;
 // returns f = [lambda^n] of the product of the series on every lane.
-template <int b>
+template <int b, bool kComp = false>
 __device__ __forceinline__ cd term_f(const cd* __restrict__ Cp, const int LDp,
                                      const cd* __restrict__ vp, const int* __restrict__ km,
                                      const double wl, const int mt, const int Ht, const int H,
@@ -518,15 +606,21 @@ __device__ __forceinline__ cd term_f(const cd* __restrict__ Cp, const int LDp,
     load_w<b>(Cp, dcol, p, q, Wr, Wi);
   }
   loop_moments<b>(Wr, Wi, dcol, vp, mt, Ht, n, p, q, lane, L);
-  spectral_series<b>(Wr, Wi, mt, n, p, q, lane, L);
+  spectral_series<b, kComp>(Wr, Wi, mt, n, p, q, lane, L);
   // f = sum_k q_k L_{n-k}: lanes over k, full-wave sum (every lane gets f)
+  if constexpr (kComp) {
+    cdd fc = cdd_zero();
+    if (lane <= n)
+      cdd_fma_hl2(fc, L.ser[lane], L.ser_lo[lane], L.ser[33 + n - lane], L.ser_lo[33 + n - lane]);
+    return cdd_round(cdd_sum_wave(fc));
+  }
   cd f = czero();
   if (lane <= n) f = cmul(L.ser[lane], L.ser[33 + n - lane]);
   return mk(sum_col8(sum_row8(f.r)), sum_col8(sum_row8(f.i)));
 }
 
 // term_f at the runtime tile bt (1 <= bt <= BMAX; uniform over the wavefront)
-template <int BMAX>
+template <int BMAX, bool kComp = false>
 __device__ __forceinline__ cd term_f_at(const int bt, const cd* __restrict__ Cp, const int LDp,
                                         const cd* __restrict__ vp, const int* __restrict__ km,
                                         const double wl, const int mt, const int Ht, const int H,
@@ -537,7 +631,7 @@ __device__ __forceinline__ cd term_f_at(const int bt, const cd* __restrict__ Cp,
 #define LH_TCASE(BB)                                                                 \
   case BB:                                                                           \
     if constexpr (BB <= BMAX)                                                        \
-      f = term_f<BB>(Cp, LDp, vp, km, wl, mt, Ht, H, n, p, q, lane, L);              \
+      f = term_f<BB, kComp>(Cp, LDp, vp, km, wl, mt, Ht, H, n, p, q, lane, L);       \
     break;
     LH_TCASE(1) LH_TCASE(2) LH_TCASE(3) LH_TCASE(4) LH_TCASE(5) LH_TCASE(6) LH_TCASE(7)
     LH_TCASE(8)
@@ -559,7 +653,7 @@ __device__ __forceinline__ cd term_f_at(const int bt, const cd* __restrict__ Cp,
 // ceil(2H'/8) lies in the bounds are evaluated (the ET term space split into
 // tile classes, each launched at its own occupancy; the classes' partial sums
 // add up).
-template <int B, bool kET>
+template <int B, bool kET, bool kComp = false>
 __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const int64_t t1,
                                          const cd* __restrict__ Cp, const cd* __restrict__ vp,
                                          Partial* __restrict__ out, LdsView& L, const int acc_dd,
@@ -598,9 +692,10 @@ __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const 
       const int mk_ = 2 * Hk;
       vred[lane] = lane < mk_ ? vp[km[lane]] : czero();
       wave_sync();
-      f = term_f_at<B>((mk_ + 7) >> 3, Cp, LDp, vred, km, wl, mk_, Hk, H, n, p, q, lane, L);
+      f = term_f_at<B, kComp>((mk_ + 7) >> 3, Cp, LDp, vred, km, wl, mk_, Hk, H, n, p, q, lane,
+                              L);
     } else {
-      f = term_f<B>(Cp, LDp, vp, nullptr, wl, m, H, H, n, p, q, lane, L);
+      f = term_f<B, kComp>(Cp, LDp, vp, nullptr, wl, m, H, H, n, p, q, lane, L);
     }
     if (acc_dd) {
       dd_add_prod(accr, coef, f.r);
@@ -690,48 +785,62 @@ __global__ void pack_kernel(const Prob* __restrict__ probs, const int64_t* __res
 #define LH_FWD_WAVES(bmax) ((bmax) <= 3 ? 4 : ((bmax) <= 4 ? 3 : ((bmax) <= 6 ? 2 : 1)))
 #endif
 
-template <int BMAX, bool kET>
-__global__ __launch_bounds__(64)
-__attribute__((amdgpu_waves_per_eu(LH_FWD_WAVES(BMAX), LH_FWD_WAVES(BMAX)))) void forward_kernel(const Prob* __restrict__ probs,
-                                                     const Item* __restrict__ items, int n_items,
-                                                     int* counter, const cd* __restrict__ ws,
-                                                     Partial* __restrict__ parts, int acc_dd,
-                                                     int nmax, cd* __restrict__ saved, int tlo,
-                                                     int thi) {
-  extern __shared__ __align__(16) char lds_raw[];
-  LdsView L = carve(lds_raw, nmax);
-  const int lane = threadIdx.x & 63;
-  for (;;) {
-    // Every lane issues the atomic (only lane 0 adds 1), so no lane-divergent
-    // region precedes the cross-lane read at the loop head; the compiler may
-    // otherwise split the loop by lane and leave lanes reading an inactive
-    // lane 0.  Lane 0's return value is unique per wavefront either way.
-    const int it = __builtin_amdgcn_readfirstlane(atomicAdd(counter, lane == 0 ? 1 : 0));
-    if (it >= n_items) break;
-    const Item I = items[it];
-    const Prob& P = probs[I.prob];
-    const int LD = 8 * P.B;
-    const cd* Cp = ws + P.c_off;
-    const cd* vp = Cp + LD * LD;
-    if constexpr (kET) {
-      // every problem: a term runs at its reduced tile, which the tile
-      // bounds keep within BMAX
-      run_item<BMAX, true>(P, I.t0, I.t1, Cp, vp, parts + I.pad, L, acc_dd, saved, tlo, thi);
-    } else {
-      switch (P.B) {
-#define LH_CASE(BB)                                                                       \
-  case BB:                                                                                \
-    if constexpr (BB <= BMAX)                                                             \
-      run_item<BB, false>(P, I.t0, I.t1, Cp, vp, parts + I.pad, L, acc_dd, saved, 1, 8);  \
-    break;
-        LH_CASE(1) LH_CASE(2) LH_CASE(3) LH_CASE(4) LH_CASE(5) LH_CASE(6) LH_CASE(7) LH_CASE(8)
-#undef LH_CASE
-        default:
-          break;
-      }
-    }
+// The forward kernels: one wavefront per workgroup takes items from the
+// work queue until it is empty.  forward_kernel evaluates in plain FP64;
+// forward_comp_kernel (the compensated-recurrence mode) forms the
+// characteristic polynomial, the two series and the final coefficient as
+// compensated dot products, at the same occupancy.  One body, stamped twice.
+#define LH_FORWARD_KERNEL(NAME, COMP)                                                          \
+  template <int BMAX, bool kET>                                                                \
+  __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(                         \
+      LH_FWD_WAVES(BMAX), LH_FWD_WAVES(BMAX)))) void NAME(const Prob* __restrict__ probs,      \
+                                                          const Item* __restrict__ items,      \
+                                                          int n_items, int* counter,           \
+                                                          const cd* __restrict__ ws,           \
+                                                          Partial* __restrict__ parts,         \
+                                                          int acc_dd, int nmax,                \
+                                                          cd* __restrict__ saved, int tlo,     \
+                                                          int thi) {                           \
+    extern __shared__ __align__(16) char lds_raw[];                                            \
+    LdsView L = carve(lds_raw, nmax);                                                          \
+    const int lane = threadIdx.x & 63;                                                         \
+    for (;;) {                                                                                 \
+      /* Every lane issues the atomic (only lane 0 adds 1), so no lane-divergent region     */ \
+      /* precedes the cross-lane read at the loop head; the compiler may otherwise split    */ \
+      /* the loop by lane and leave lanes reading an inactive lane 0.  Lane 0's return      */ \
+      /* value is unique per wavefront either way.                                          */ \
+      const int it = __builtin_amdgcn_readfirstlane(atomicAdd(counter, lane == 0 ? 1 : 0));    \
+      if (it >= n_items) break;                                                                \
+      const Item I = items[it];                                                                \
+      const Prob& P = probs[I.prob];                                                           \
+      const int LD = 8 * P.B;                                                                  \
+      const cd* Cp = ws + P.c_off;                                                             \
+      const cd* vp = Cp + LD * LD;                                                             \
+      if constexpr (kET) {                                                                     \
+        /* every problem: a term runs at its reduced tile, which the tile bounds keep     */   \
+        /* within BMAX                                                                    */   \
+        run_item<BMAX, true, COMP>(P, I.t0, I.t1, Cp, vp, parts + I.pad, L, acc_dd, saved,     \
+                                   tlo, thi);                                                  \
+      } else {                                                                                 \
+        switch (P.B) {                                                                         \
+          LH_FWD_CASE(1, COMP) LH_FWD_CASE(2, COMP) LH_FWD_CASE(3, COMP) LH_FWD_CASE(4, COMP)  \
+          LH_FWD_CASE(5, COMP) LH_FWD_CASE(6, COMP) LH_FWD_CASE(7, COMP) LH_FWD_CASE(8, COMP)  \
+          default:                                                                             \
+            break;                                                                             \
+        }                                                                                      \
+      }                                                                                        \
+    }                                                                                          \
   }
-}
+#define LH_FWD_CASE(BB, COMP)                                                               \
+  case BB:                                                                                  \
+    if constexpr (BB <= BMAX)                                                               \
+      run_item<BB, false, COMP>(P, I.t0, I.t1, Cp, vp, parts + I.pad, L, acc_dd, saved, 1,  \
+                                8);                                                         \
+    break;
+LH_FORWARD_KERNEL(forward_kernel, false)
+LH_FORWARD_KERNEL(forward_comp_kernel, true)
+#undef LH_FWD_CASE
+#undef LH_FORWARD_KERNEL
 
 #ifdef LH_COMMON_KERNELS
 // Sum the item partials of each problem in item order (double-double),

@@ -64,6 +64,12 @@ inline size_t lds_bytes_for(int nmax) {
   const size_t NP = nmax + 1, NR = nmax + 2;
   return 16 * (65 + 65 + 64 + 128 + 33 + 66) + 8 * 8 + 16 * NP * NR;
 }
+// the compensated-recurrence forward: also the low parts of the ring and of
+// the two series
+inline size_t lds_bytes_comp(int nmax) {
+  const size_t NP = nmax + 1, NR = nmax + 2;
+  return lds_bytes_for(nmax) + 16 * (NP * NR + 66);
+}
 
 // Host planner --------------------------------------------------------------
 struct PairPlan {

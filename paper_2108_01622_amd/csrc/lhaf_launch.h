@@ -31,6 +31,10 @@ struct PersistArgs {
 template <int B>
 hipError_t launch_forward(const PersistArgs& a, const cd* ws, Partial* parts, int acc_dd,
                           cd* saved, int et, int tlo, int thi);
+// forward_comp_kernel<B, et>: the same with compensated recurrences
+template <int B>
+hipError_t launch_forward_comp(const PersistArgs& a, const cd* ws, Partial* parts, int acc_dd,
+                               cd* saved, int et, int tlo, int thi);
 // backward_kernel<B>: item gradient slots; per-wavefront scratch; with
 // `parts` (fused pass) also the item partials of the value
 template <int B, bool kStg>
@@ -48,6 +52,8 @@ hipError_t launch_real(const PersistArgs& a, const double* ws, Partial* parts, i
 // (occupancy query of the runtime; 0 if the query fails).
 template <int B>
 int resident_forward(size_t lds, int et);
+template <int B>
+int resident_forward_comp(size_t lds, int et);
 template <int B, bool kStg>
 int resident_backward_as(size_t lds);
 #if defined(LH_STAGE_MAX_B) && defined(LH_STAGE_RECOMPUTE_MAX_B)

@@ -4,13 +4,14 @@
 //   LH_FAMILY 1 backward_kernel<LH_TILE> (+ occupancy query)
 //   LH_FAMILY 2 multi_kernel<LH_TILE, 0 and 1>
 //   LH_FAMILY 3 real::real_kernel<LH_TILE>
+//   LH_FAMILY 4 forward_comp_kernel<LH_TILE, ET and FDS> (+ occupancy query)
 #include <hip/hip_runtime.h>
 
 #ifndef LH_TILE
 #error "LH_TILE (register tile 1..8) must be defined"
 #endif
 #ifndef LH_FAMILY
-#error "LH_FAMILY (0 forward, 1 backward, 2 multi, 3 real) must be defined"
+#error "LH_FAMILY (0 forward, 1 backward, 2 multi, 3 real, 4 compensated forward) must be defined"
 #endif
 
 // Code-generation choices of the wavefront reductions and the Hessenberg
@@ -127,6 +128,31 @@ hipError_t launch_real(const PersistArgs& a, const double* ws, Partial* parts, i
   return hipGetLastError();
 }
 template hipError_t launch_real<LH_TILE>(const PersistArgs&, const double*, Partial*, int);
+#elif LH_FAMILY == 4
+template <int B>
+hipError_t launch_forward_comp(const PersistArgs& a, const cd* ws, Partial* parts, int acc_dd,
+                               cd* saved, int et, int tlo, int thi) {
+  if (et)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(forward_comp_kernel<B, true>), dim3(a.grid), dim3(64),
+                       a.lds, a.stream, a.probs, a.items, a.n_items, a.counter, ws, parts, acc_dd,
+                       a.nmax, saved, tlo, thi);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(forward_comp_kernel<B, false>), dim3(a.grid), dim3(64),
+                       a.lds, a.stream, a.probs, a.items, a.n_items, a.counter, ws, parts, acc_dd,
+                       a.nmax, saved, 1, 8);
+  return hipGetLastError();
+}
+template <int B>
+int resident_forward_comp(size_t lds, int et) {
+  int blocks = 0;
+  const void* fn = et ? reinterpret_cast<const void*>(&forward_comp_kernel<B, true>)
+                      : reinterpret_cast<const void*>(&forward_comp_kernel<B, false>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, 64, lds) != hipSuccess) return 0;
+  return blocks;
+}
+template hipError_t launch_forward_comp<LH_TILE>(const PersistArgs&, const cd*, Partial*, int,
+                                                 cd*, int, int, int);
+template int resident_forward_comp<LH_TILE>(size_t, int);
 #endif
 
 }  // namespace lh

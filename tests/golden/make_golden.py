@@ -7,6 +7,7 @@ Each entry records how it was computed.  Methods:
   memo_f128      definition, memoised recursion, __float128
   fds_f64        finite-difference sieve, explicit matrix powers, double + Neumaier
   fds_f128       same in __float128
+  fds_f128 lhafmix  mixed-state lhafmix (App. B.2), FDS in __float128
   block_f128     block-diagonal A1 (+) A2: lhaf(A1) * lhaf(A2), each half FDS in
                  __float128 (the paper's own accuracy protocol, App. B.4)
 The file is updated incrementally (existing keys are kept unless --force).
@@ -108,6 +109,16 @@ def jobs():
             v, ab = O.lhaf_sum(A1, gs[k], mode="fds", prec="f64", with_abs=True)
             return dict(method="fds_f64", value=cx(v), abs_sum=ab, sha256=I.sha256_of(A1, gs[k]))
         J[f"gammas40/{k}"] = gjob
+    # mixed state of 14 modes, photon numbers capped at 2 sum n = 40, in the
+    # pairing (i, M + i) of lhafmix (App. B.2): kappa = 4.4e6
+    def mixjob(inst=0):
+        A, g, n = I.mixed_state(14, inst)
+        while 2 * n.sum() > 40:
+            n[np.argmax(n)] -= 1
+        v = O.lhafmix(A, g, n, mode="fds", prec="f128")
+        return dict(method="fds_f128 lhafmix", value=cx(v), n=[int(x) for x in n],
+                    sha256=I.sha256_of(A, g))
+    J["mixed14/0/f128"] = mixjob
     for n in (24, 40):
         def rjob(n=n):
             a, g = I.real_nonneg(n, 0)

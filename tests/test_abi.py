@@ -88,6 +88,37 @@ def test_invalid_arguments(L):
     assert L.lib().lhaf_term_count(2, L.host_ptr(r), 1) == -1
 
 
+def test_compensated_mode_gating(L):
+    """acc = LH_ACC_DD_COMP is accepted by the value entry points only; the
+    others refuse it before any device work (LH_EUNSUPPORTED), and an unknown
+    accumulation mode is an invalid argument."""
+    import ctypes
+    src = open(os.path.join(ROOT, "include", "lhaf.h")).read()
+    assert int(re.search(r"#define LH_ACC_DD_COMP (\d+)", src).group(1)) == L.LH_ACC_DD_COMP
+    lib = L.lib()
+    o = L.make_opts(acc="ddc")
+    EUNS = 5
+    assert lib.lhaf_backward(1, None, 2, 4, None, 2, None, None, None, None, None, None, 1, None, 0,
+                             ctypes.byref(o), None) == EUNS
+    assert lib.lhaf_real(None, 2, None, None, 1, None, None, ctypes.byref(o), None) == EUNS
+    assert lib.lhaf_chain(None, 2, None, None, 1, 0, 2, None, None, ctypes.byref(o), None) == EUNS
+    assert lib.lhaf_gammas(None, 2, None, 2, None, 1, 1, None, None, ctypes.byref(o), None) == EUNS
+    og = L.make_opts(acc="ddc")
+    og.grads = ctypes.c_void_p(16)
+    og.grads_count = 1
+    assert lib.lhaf_batched(1, None, 2, 4, None, 2, None, None, None, None, None, None, 0,
+                            ctypes.byref(og), None) == EUNS
+    os_ = L.make_opts(acc="ddc")
+    os_.saved = ctypes.c_void_p(16)
+    os_.saved_count = 1
+    assert lib.lhaf(None, 2, None, 2, None, None, ctypes.byref(os_), None) == EUNS
+    bad = L.make_opts()
+    bad.acc = 3
+    assert lib.lhaf(None, 2, None, 2, None, None, ctypes.byref(bad), None) == 1
+    # the value entry points accept it (a null output is then the first error)
+    assert lib.lhaf(None, 2, None, 2, None, None, ctypes.byref(o), None) == 1
+
+
 def test_saved_count(L):
     """Entries of the per-term coefficient store: sum over problems of terms x n."""
     import ctypes
