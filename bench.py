@@ -452,19 +452,27 @@ def main():
         tf52 = canonical_flops(52, 26) * T52 / t52 / 1e12
         ent = {"workload": "block52/0 (A1 (+) A2, N=52, FDS dd), full sum", "terms_per_s": T52 / t52,
                "tflops": tf52, "frac": tf52 / FP64_PEAK_TFLOPS, "seconds": t52}
+        # the same sum with the characteristic polynomial and the series in
+        # double-double (acc "ddc")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        v52c = api.lhaf(a52, q52, acc="ddc").item()
+        t52c = time.perf_counter() - t
+        ent["ddc_terms_per_s"] = T52 / t52c
         if "block52/0" in gold:
             ref = complex(*gold["block52/0"]["value"])
             ent["rel_err_vs_oracle"] = abs(v52 - ref) / abs(ref)
+            ent["ddc_rel_err_vs_oracle"] = abs(v52c - ref) / abs(ref)
             ent["oracle"] = "__float128 FDS of both halves, multiplied"
         return ent
 
-    extra("n52_forward_full", 25, n52_full)
+    extra("n52_forward_full", 35, n52_full)
 
     def modes():
         A8, g8 = A[:8], g[:8]
         out = {}
         for sm in ("fds", "et"):
-            for am in ("dd", "fp64"):
+            for am in ("dd", "fp64", "ddc"):
                 dt = timed_once(lambda: api.lhaf_batched(A8, g8, sum=sm, acc=am))
                 T8 = 8 * _binding.term_count(N, sum=sm)
                 fl = 8 * (et_flops_per_lhaf(N) if sm == "et" else F * _binding.term_count(N))

@@ -439,8 +439,14 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
   if constexpr (!kStage)
     while (s > 2 && (s - 2) + (n + s - 2) / (s - 1) <= (s - 1) + (n + s - 1) / s) --s;
   const int Q = (n + s - 1) / s - 1;
-  dd accr = {0.0, 0.0}, acci = {0.0, 0.0};
-  double sabs = 0.0;
+  // The item's value partial (fused pass) lives in LDS, in the scalar slots
+  // after the reflector's (hr, lr, hi, li, abs), read and written by lane 0
+  // only: in registers it would stay live through the whole term.
+  double* vacc = L.sc + 3;
+  if (part && lane0 == 0) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) vacc[k] = 0.0;
+  }
 
   TermIter it = term_begin(P, t0, lane0);
   for (int64_t t = t0; t < t1; ++t) {
@@ -489,14 +495,21 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
         cd f = czero();
         if (lane <= n) f = cmul(L.ser[lane], L.ser[33 + n - lane]);
         f = mk(sum_col8(sum_row8(f.r)), sum_col8(sum_row8(f.i)));
-        if (acc_dd) {
-          dd_add_prod(accr, coef, f.r);
-          dd_add_prod(acci, coef, f.i);
-        } else {
-          accr.hi = fma(coef, f.r, accr.hi);
-          acci.hi = fma(coef, f.i, acci.hi);
+        if (lane0 == 0) {
+          dd accr = {vacc[0], vacc[1]}, acci = {vacc[2], vacc[3]};
+          if (acc_dd) {
+            dd_add_prod(accr, coef, f.r);
+            dd_add_prod(acci, coef, f.i);
+          } else {
+            accr.hi = fma(coef, f.r, accr.hi);
+            acci.hi = fma(coef, f.i, acci.hi);
+          }
+          vacc[0] = accr.hi;
+          vacc[1] = accr.lo;
+          vacc[2] = acci.hi;
+          vacc[3] = acci.lo;
+          vacc[4] = fma(fabs(coef), sqrt(cabs2(f)), vacc[4]);
         }
-        sabs = fma(fabs(coef), sqrt(cabs2(f)), sabs);
       }
     }
     lane_sync<kStage>();
@@ -587,11 +600,11 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
   G[LD * LD + lane0] = gv;
   if (part && lane0 == 0) {
     Partial pr;
-    pr.hr = accr.hi;
-    pr.hi = acci.hi;
-    pr.lr = accr.lo;
-    pr.li = acci.lo;
-    pr.abs_sum = sabs;
+    pr.hr = vacc[0];
+    pr.hi = vacc[2];
+    pr.lr = vacc[1];
+    pr.li = vacc[3];
+    pr.abs_sum = vacc[4];
     pr.pad0 = pr.pad1 = pr.pad2 = 0.0;
     *part = pr;
   }

@@ -663,8 +663,14 @@ __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const 
   int* km = reinterpret_cast<int*>(L.wv);  // free until the Hessenberg phase
   cd* vred = L.xb + 64;                    // overwritten only after loop_moments read it
   TermIter it = term_begin(P, t0, lane0);
-  dd accr = {0.0, 0.0}, acci = {0.0, 0.0};
-  double sabs = 0.0;
+  // The item's partial lives in LDS, in the scalar slots after the
+  // reflector's (hr, lr, hi, li, abs), read and written by lane 0 only: in
+  // registers it would stay live through the whole term.
+  double* vacc = L.sc + 3;
+  if (lane0 == 0) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) vacc[k] = 0.0;
+  }
 
   for (int64_t t = t0; t < t1; ++t) {
     // lane index of this term (optionally opaque, see LH_OPAQUE_TERM)
@@ -697,24 +703,31 @@ __device__ __forceinline__ void run_item(const Prob& P, const int64_t t0, const 
     } else {
       f = term_f<B, kComp>(Cp, LDp, vp, nullptr, wl, m, H, H, n, p, q, lane, L);
     }
-    if (acc_dd) {
-      dd_add_prod(accr, coef, f.r);
-      dd_add_prod(acci, coef, f.i);
-    } else {
-      accr.hi = fma(coef, f.r, accr.hi);
-      acci.hi = fma(coef, f.i, acci.hi);
+    if (lane0 == 0) {
+      dd accr = {vacc[0], vacc[1]}, acci = {vacc[2], vacc[3]};
+      if (acc_dd) {
+        dd_add_prod(accr, coef, f.r);
+        dd_add_prod(acci, coef, f.i);
+      } else {
+        accr.hi = fma(coef, f.r, accr.hi);
+        acci.hi = fma(coef, f.i, acci.hi);
+      }
+      vacc[0] = accr.hi;
+      vacc[1] = accr.lo;
+      vacc[2] = acci.hi;
+      vacc[3] = acci.lo;
+      vacc[4] = fma(fabs(coef), sqrt(cabs2(f)), vacc[4]);
     }
-    sabs = fma(fabs(coef), sqrt(cabs2(f)), sabs);
     if (saved && lane >= 1 && lane <= n) saved[P.s_off + (t - P.t0) * n + (lane - 1)] = series_coef(L, n, lane);
     wave_sync();
   }
   if (lane0 == 0) {
     Partial pr;
-    pr.hr = accr.hi;
-    pr.hi = acci.hi;
-    pr.lr = accr.lo;
-    pr.li = acci.lo;
-    pr.abs_sum = sabs;
+    pr.hr = vacc[0];
+    pr.hi = vacc[2];
+    pr.lr = vacc[1];
+    pr.li = vacc[3];
+    pr.abs_sum = vacc[4];
     pr.pad0 = pr.pad1 = pr.pad2 = 0.0;
     *out = pr;
   }
