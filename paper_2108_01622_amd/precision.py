@@ -26,9 +26,28 @@ ROOT = os.path.dirname(HERE)
 GOLD = os.path.join(ROOT, "tests", "golden", "oracle_values.json")
 
 
-def measure(N: int, instances, modes, log=sys.stderr):
+def _sliced(api, _binding, At, gt, N, sm, am, slices, label, log):
+    """lhaf as `slices` consecutive term ranges (each scaled: its share of the
+    sum), combined exactly from their double-double parts; a progress line
+    per range.  Returns (value, summed err_est)."""
+    import math
+    T = _binding.term_count(N, sum=sm)
+    re, im, est = [], [], 0.0
+    for i in range(slices):
+        t0, t1 = i * T // slices, (i + 1) * T // slices
+        v, e, lo = api.lhaf(At, gt, sum=sm, acc=am, term_begin=t0, term_end=t1,
+                            return_error=True, return_lo=True)
+        v, lo = complex(v.item()), complex(lo.item())
+        re += [v.real, lo.real]
+        im += [v.imag, lo.imag]
+        est += e.item()
+        print(f"[precision] {label} terms [{t0}, {t1}) done", file=log, flush=True)
+    return complex(math.fsum(re), math.fsum(im)), est
+
+
+def measure(N: int, instances, modes, log=sys.stderr, slices=1):
     import torch
-    from . import api, inputs
+    from . import _binding, api, inputs
     gold = json.load(open(GOLD))
     rows = []
     for k in instances:
@@ -44,8 +63,11 @@ def measure(N: int, instances, modes, log=sys.stderr):
             print(f"[precision] {key} {mode} ...", file=log, flush=True)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            v, e = api.lhaf(At, gt, sum=sm, acc=am, return_error=True)
-            v, e = v.item(), e.item()
+            if slices > 1:
+                v, e = _sliced(api, _binding, At, gt, N, sm, am, slices, f"{key} {mode}", log)
+            else:
+                v, e = api.lhaf(At, gt, sum=sm, acc=am, return_error=True)
+                v, e = v.item(), e.item()
             dt = time.perf_counter() - t
             rel = abs(v - ref) / abs(ref)
             rows.append(dict(key=key, mode=mode, rel=rel, err_est_rel=e / abs(ref), seconds=dt))
@@ -77,10 +99,12 @@ def main(argv=None):
     ap.add_argument("--from60", type=int, default=0, help="first block60 instance")
     ap.add_argument("--modes", nargs="*", default=["fds/dd", "fds/fp64", "et/dd", "et/fp64"])
     ap.add_argument("--modes60", nargs="*", default=["fds/dd", "fds/fp64"])
+    ap.add_argument("--slices60", type=int, default=1,
+                    help="evaluate each N = 60 sum as this many term ranges (progress per range)")
     a = ap.parse_args(argv)
     rows = measure(52, range(a.n52), a.modes)
     if a.n60 > 0:
-        rows += measure(60, range(a.from60, a.from60 + a.n60), a.modes60)
+        rows += measure(60, range(a.from60, a.from60 + a.n60), a.modes60, slices=a.slices60)
     sys.stdout.write(table(rows))
 
 
