@@ -56,7 +56,9 @@ def test_mixed_state_moderate(T, api, orc, inst):
     got, err = got.item(), err.item()
     # the library's estimate takes a per-term rounding of 8(m+1) u of
     # |c_t f_t|, so the bound scales with this pairing's kappa (instance 0:
-    # kappa 4.9e6, m = 20, measured 1.6e-11 = 6 (m+1) u kappa |lhaf|)
+    # kappa 4.4e6, m = 20, measured 6.6e-8 relative = 6 (m+1) u kappa; the
+    # double-double recurrences of acc="ddc" are tested on this case in
+    # test_gpu_compensated.py)
     assert abs(got - want) <= err, (got, want, err)
     assert rel(got, want) < max(1e-10, 2e-14 * ab / abs(want))
     # the greedy pairing of the same (n, n) pattern is far better conditioned
