@@ -38,7 +38,11 @@ def lhaf(A: torch.Tensor, gamma: torch.Tensor | None = None, r=None, *, sum: str
          schedule: int = -1, return_error: bool = False, return_lo: bool = False,
          workspace: torch.Tensor | None = None):
     """Loop hafnian of one matrix.  gamma=None takes gamma = diag(A).  With r
-    (host integer multiplicities) this is lhaf_repeated: lhaf(A_r, gamma_r)."""
+    (host integer multiplicities) this is lhaf_repeated: lhaf(A_r, gamma_r).
+    acc: "dd" double-double accumulation of the signed sum (default), "fp64"
+    plain, "ddc" double-double accumulation and each term's characteristic
+    polynomial and series recurrences in double-double (ill-conditioned sums;
+    values only, not with gradients)."""
     A = _dev_c128(A, "A")
     if A.dim() != 2 or A.shape[0] != A.shape[1]:
         raise ValueError("A must be square")
