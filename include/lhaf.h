@@ -69,14 +69,17 @@ typedef int32_t lh_status;
 #define LH_ACC_FP64 0 /* plain double accumulation of the signed term sum */
 #define LH_ACC_DD 1   /* double-double (TwoProd/TwoSum) accumulation */
 /* LH_ACC_DD_COMP: double-double accumulation, and every term's characteristic
-   polynomial (the cofactor recurrence on its Hessenberg form), the two
-   power-series recurrences and the final lambda^n coefficient formed
-   as compensated dot products (each value as if computed in twice the working
-   precision and rounded once; Ogita, Rump and Oishi 2005).  About ten times
-   smaller per-term error on ill-conditioned terms, at a higher cost per term.
-   Values only: lhaf, lhaf_repeated, lhaf_batched (not fused, no saved),
-   lhaf_batched_noalloc and lhaf_mixed; the other entry points return
-   LH_EUNSUPPORTED.  err_est is the same a-priori estimate as for LH_ACC_DD. */
+   polynomial (the cofactor recurrence on its Hessenberg form) and the two
+   power-series recurrences kept in double-double: each new value is a
+   compensated dot product of double-double operands (TwoProd / TwoSum,
+   Ogita, Rump and Oishi 2005) stored unrounded, and the final lambda^n
+   coefficient is formed the same way and rounded once.  The Hessenberg
+   reduction and the loop moments stay FP64.  Per-term errors of
+   ill-conditioned terms drop by about two orders of magnitude; a term costs
+   1.4x to 1.8x as much (N = 52 .. 40).  Values only: lhaf, lhaf_repeated,
+   lhaf_batched (not fused, no saved), lhaf_batched_noalloc and lhaf_mixed;
+   the other entry points return LH_EUNSUPPORTED.  err_est is the same
+   a-priori estimate as for LH_ACC_DD. */
 #define LH_ACC_DD_COMP 2
 
 typedef struct {
