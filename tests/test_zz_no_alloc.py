@@ -21,13 +21,13 @@ def T():
     return torch
 
 
-def _call(T, name, A, g, idx, off, sum_mode="fds"):
+def _call(T, name, A, g, idx, off, sum_mode="fds", acc="dd"):
     from paper_2108_01622_amd import _binding as Bn
     L = Bn.lib()
     B = len(off) - 1
     out = T.empty(B, dtype=T.complex128, device="cuda")
     err = T.empty(B, dtype=T.float64, device="cuda")
-    o = Bn.make_opts(sum_mode)
+    o = Bn.make_opts(sum_mode, acc)
     st = ctypes.c_void_p(T.cuda.current_stream().cuda_stream)
     lda = A.shape[-1]
     sA = 0 if A.dim() == 2 else A.shape[1] * A.shape[2]
@@ -62,12 +62,14 @@ def test_noalloc_matches_batched_two_calls(T):
     off2 = np.array([0, 9, 23, 43], dtype=np.int64)
     for A, g, idx, off in ((A1, g1, None, off1), (A2, g2, idx2, off2)):
         for mode in ("fds", "et"):
-            s0, want, werr = _call(T, "lhaf_batched", A, g, idx, off, mode)
-            s1, got, gerr = _call(T, "lhaf_batched_noalloc", A, g, idx, off, mode)
-            print(f"[case] noalloc B={len(off) - 1} {mode} status {s0} {s1}", flush=True)
-            assert s0 == 0 and s1 == 0
-            assert np.array_equal(got, want), np.max(np.abs(got - want) / np.abs(want))
-            assert np.array_equal(gerr, werr)
+            # "ddc": the double-double recurrence kernels, with their larger LDS
+            for acc in ("dd", "ddc"):
+                s0, want, werr = _call(T, "lhaf_batched", A, g, idx, off, mode, acc)
+                s1, got, gerr = _call(T, "lhaf_batched_noalloc", A, g, idx, off, mode, acc)
+                print(f"[case] noalloc B={len(off) - 1} {mode} {acc} status {s0} {s1}", flush=True)
+                assert s0 == 0 and s1 == 0
+                assert np.array_equal(got, want), np.max(np.abs(got - want) / np.abs(want))
+                assert np.array_equal(gerr, werr)
 
 
 def test_noalloc_rejects_oversize_batch(T):
