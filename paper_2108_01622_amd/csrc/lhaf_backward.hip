@@ -405,7 +405,7 @@ __device__ __forceinline__ void combine_powers(double (&Rr)[B][B], double (&Ri)[
 // the value: the recomputed series give f = sum_k q_k L_{n-k} of every term,
 // added as c_t f_t into a double-double (acc_dd) or plain partial, exactly as
 // the forward kernel does.
-template <int B, bool kStage>
+template <int B, bool kStage, bool kRankLate = false>
 __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, const int64_t t1,
                                              const cd* __restrict__ Cp,
                                              const cd* __restrict__ vp, cd* __restrict__ G,
@@ -515,25 +515,30 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
     lane_sync<kStage>();
 
     double Rr[B][B], Ri[B][B];
-    // ---- rank-one terms sum_i beta_i alpha_i^T (while the Krylov vectors
-    // are resident), added to the item gradient ahead of P(W)
+    // ---- rank-one terms sum_i beta_i alpha_i^T.  Added to the item gradient
+    // here, while the Krylov vectors are resident (a staged tile's P(W)
+    // operand overwrites them in LDS); with kRankLate (unstaged, vectors in
+    // the global scratch) they are added to P(W) in registers after the
+    // products instead, one read-modify-write of the gradient slot per term.
+    if constexpr (!kRankLate) {
 #pragma unroll
-    for (int a = 0; a < B; ++a)
+      for (int a = 0; a < B; ++a)
 #pragma unroll
-      for (int k = 0; k < B; ++k) Rr[a][k] = Ri[a][k] = 0.0;
-    if constexpr (kStage) {
-      rank_terms<B, S>(Rr, Ri, bv, acoef, dcol_k, m, H, n, p, q, lane, L.xb);
-    } else {
-      double dcol[B];
-      column_weights<B>(wl, m, H, q, dcol);
-      rank_terms<B, S>(Rr, Ri, bv, acoef, dcol, m, H, n, p, q, lane, L.xb);
-    }
-    if constexpr (kStage) {
-      accumulate_g<B>(G, coef, drow_k, Rr, Ri, p, q);
-    } else {
-      double drow[B];
-      row_weights<B>(wl, m, H, p, drow);
-      accumulate_g<B>(G, coef, drow, Rr, Ri, p, q);
+        for (int k = 0; k < B; ++k) Rr[a][k] = Ri[a][k] = 0.0;
+      if constexpr (kStage) {
+        rank_terms<B, S>(Rr, Ri, bv, acoef, dcol_k, m, H, n, p, q, lane, L.xb);
+      } else {
+        double dcol[B];
+        column_weights<B>(wl, m, H, q, dcol);
+        rank_terms<B, S>(Rr, Ri, bv, acoef, dcol, m, H, n, p, q, lane, L.xb);
+      }
+      if constexpr (kStage) {
+        accumulate_g<B>(G, coef, drow_k, Rr, Ri, p, q);
+      } else {
+        double drow[B];
+        row_weights<B>(wl, m, H, p, drow);
+        accumulate_g<B>(G, coef, drow, Rr, Ri, p, q);
+      }
     }
     // ---- d f / d v_l = sum_k a_k (alpha_{k-1}[l] + d_{pair(l)} b_{k-1}[partner(l)])
     //                  = 2 sum_k a_k d_{pair(l)} b_{k-1}[partner(l)]
@@ -591,6 +596,11 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
     if constexpr (kStage) {
       accumulate_g<B>(G, coef, drow_k, Rr, Ri, p, q);
     } else {
+      if constexpr (kRankLate) {
+        double dcol[B];
+        column_weights<B>(wl, m, H, q, dcol);
+        rank_terms<B, S>(Rr, Ri, bv, acoef, dcol, m, H, n, p, q, lane, L.xb);
+      }
       double drow[B];
       row_weights<B>(wl, m, H, p, drow);
       accumulate_g<B>(G, coef, drow, Rr, Ri, p, q);
@@ -610,6 +620,12 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
   }
 }
 
+// The unstaged instance's own tile (4 or 5) adds the rank-one terms to P(W)
+// in registers and updates the gradient slot once per term; the larger
+// tiles keep the separate update, where the late form raised the scratch.
+#ifndef LH_BWD_RANK_LATE
+#define LH_BWD_RANK_LATE(bb, bmax, stg) (!(stg) && (bb) == (bmax) && (bmax) <= 5)
+#endif
 #ifndef LH_BWD_WAVES
 #define LH_BWD_WAVES(bmax, stg) \
   ((bmax) <= 1 ? 4 : ((bmax) <= 3 ? 2 : ((bmax) <= 5 && !(stg) ? 2 : 1)))
@@ -646,7 +662,7 @@ __global__ LH_BWD_ATTR void backward_kernel(const Prob* __restrict__ probs,
 #define LH_BCASE(BB)                                                                   \
   case BB:                                                                             \
     if (BB <= BMAX)                                                                    \
-      run_item_bwd<(BB <= BMAX ? BB : 1), kStg>(                                         \
+      run_item_bwd<(BB <= BMAX ? BB : 1), kStg, LH_BWD_RANK_LATE(BB, BMAX, kStg)>(       \
           P, I.t0, I.t1, Cp, vp, G, scr, L, saved, parts ? parts + I.pad : nullptr, acc_dd); \
     break;
       LH_BCASE(1)
