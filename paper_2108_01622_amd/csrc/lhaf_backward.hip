@@ -620,11 +620,13 @@ __device__ __forceinline__ void run_item_bwd(const Prob& P, const int64_t t0, co
   }
 }
 
-// The unstaged instance's own tile (4 or 5) adds the rank-one terms to P(W)
-// in registers and updates the gradient slot once per term; the larger
-// tiles keep the separate update, where the late form raised the scratch.
+// The unstaged instances add the rank-one terms to P(W) in registers and
+// update the gradient slot once per term, at their own tile only (measured
+// on MI355X, fused pass M terms/s, late vs separate: N = 40 4.54 vs 4.40,
+// N = 48 1.80 vs 1.72, N = 64 0.270 vs 0.265); tile 7 keeps the separate
+// update (N = 52 1.00 vs 1.04).
 #ifndef LH_BWD_RANK_LATE
-#define LH_BWD_RANK_LATE(bb, bmax, stg) (!(stg) && (bb) == (bmax) && (bmax) <= 5)
+#define LH_BWD_RANK_LATE(bb, bmax, stg) (!(stg) && (bb) == (bmax) && (bmax) != 7)
 #endif
 #ifndef LH_BWD_WAVES
 #define LH_BWD_WAVES(bmax, stg) \
